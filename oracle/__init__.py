@@ -1,0 +1,12 @@
+"""Plain CPU oracle for higher-order truss decomposition.
+
+TEST INFRASTRUCTURE ONLY: the slow, obviously correct reference that the GPU
+library is checked against.  Only the test suite, the smoke check and the
+benchmark's CPU-baseline leg may import it.  It shares no code with the GPU
+library (``paper_2411_06405_amd``) and never imports it.
+"""
+from .oracle import (OracleError, build, certify, decompose, h_support, lib_path)
+from .brute import brute_trussness, brute_h_support
+
+__all__ = ["OracleError", "build", "certify", "decompose", "h_support", "lib_path",
+           "brute_trussness", "brute_h_support"]
