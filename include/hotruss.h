@@ -1,0 +1,138 @@
+/*
+ * hotruss.h -- C ABI of libhotruss, higher-order (k,h)-truss decomposition on
+ * AMD Instinct MI355X (gfx950).
+ *
+ * Problem (paper, Section 2, problem statement): given an undirected simple
+ * graph G = (V, E) and a hop threshold h >= 1, compute the h-trussness
+ * t(e,h) of every edge, the largest k such that the (k,h)-truss contains e.
+ *   N_S(x,h)    vertices other than x within h hops of x, hops counted over
+ *               the edges of the current edge set S;
+ *   sup_S(e,h)  |N_S(u,h) intersect N_S(v,h)| for e = (u,v)        (Def. 3);
+ *   (k,h)-truss the maximal S with sup_S(e,h) >= k-2 on all of S   (Def. 4).
+ * Neither endpoint of e is ever one of its common h-neighbours; paths may pass
+ * through either endpoint; S is an edge subset.
+ *
+ * Conventions shared by every entry point:
+ *   Graph     symmetric CSR: row_ptr[n+1] and col_idx[2m] (uint32), both
+ *             directions of each edge stored, rows strictly ascending, no
+ *             self-loops, no duplicates; isolated vertices allowed.
+ *   m         number of undirected edges = row_ptr[n] / 2, below 2^31.
+ *   Edge ids  canonical upper-triangle order: for x = 0..n-1 ascending, each
+ *             neighbour y > x ascending; edge (x,y) has the rank of that pair.
+ *             Every per-edge output is laid out in this order.
+ *   Memory    unless a comment says "host", pointers are DEVICE pointers on
+ *             the current HIP device, owned by the caller; the library never
+ *             allocates device memory, it carves everything from the caller's
+ *             workspace and keeps no pointer after the call returns (sessions
+ *             excepted, see below).
+ *   Streams   work is enqueued on `stream`.  Calls return after the work has
+ *             completed on that stream unless stated otherwise.
+ *   Errors    argument errors return at once, before any device work.  The
+ *             CSR is always validated on the device (row_ptr monotone and
+ *             row_ptr[n] == 2m, ids < n, rows strictly ascending, no loops,
+ *             symmetric); a malformed CSR returns HO_ERR_BAD_CSR and leaves
+ *             the outputs unspecified.  m == 0 returns HO_OK with no work.
+ */
+#ifndef HOTRUSS_H
+#define HOTRUSS_H
+
+#include <stddef.h>
+#include <stdint.h>
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    HO_OK = 0,
+    HO_ERR_INVALID_ARG = -1, /* NULL pointer, h == 0, m too large, ...        */
+    HO_ERR_BAD_CSR = -2,     /* device-side CSR validation failed             */
+    HO_ERR_WORKSPACE = -3,   /* workspace smaller than the query returned     */
+    HO_ERR_HIP = -4,         /* a HIP runtime call failed                     */
+    HO_ERR_BUDGET = -5,      /* session: request does not fit the pool now    */
+    HO_ERR_CANCELLED = -6,   /* session: ticket was cancelled                 */
+    HO_ERR_BUSY = -7,        /* session: no free slot                         */
+    HO_ERR_NOT_FOUND = -8,   /* session: unknown ticket                       */
+    HO_ERR_INTERNAL = -9     /* an internal invariant failed (a bug)          */
+} hoStatus;
+
+/* Optional knobs; pass NULL for defaults.  Every setting gives the same
+ * results; they only change speed and workspace size. */
+typedef struct {
+    uint32_t word_bits;       /* bitset load width per lane: 64 or 128 (0 = auto)        */
+    uint32_t dense_threshold; /* ball build: frontier degree sum above which a row is
+                                 built by OR-ing neighbour rows instead of scattering
+                                 the frontier's adjacency (0 = auto)                      */
+    uint32_t edges_per_wave;  /* initial h-support: edges sharing one wavefront, 1..16
+                                 (0 = auto)                                              */
+    uint32_t flags;           /* HO_FLAG_*                                               */
+    uint32_t event_capacity;  /* per-level ball-change event list entries; a round that
+                                 overflows it falls back to full bitset scans (0 = auto)  */
+    uint32_t grid_blocks;     /* workgroups of the round driver (0 = auto)               */
+} hoTuning;
+
+#define HO_FLAG_HOST_LOOP 0x1u  /* drive peel rounds from the host, one round per
+                                   launch sequence (debugging; slower)                */
+#define HO_FLAG_STATS 0x2u      /* keep per-run counters for hoTrussLastStats          */
+
+/* Work counters of the last decomposition on this host thread. */
+typedef struct {
+    uint64_t rounds;        /* peel rounds that removed at least one edge          */
+    uint64_t levels;        /* distinct levels k visited                           */
+    uint64_t events;        /* ball-change events at the top level h               */
+    uint64_t overflows;     /* rounds that fell back to full event scans           */
+    double   device_ms;     /* device time of the whole call (HIP events)          */
+} hoStats;
+
+/* Bytes of device workspace hoTrussDecompose / hoTrussHSupport need for a
+ * graph with n vertices, m undirected edges and hop threshold h.  Dominated by
+ * 2h bitset arrays of n x ceil(n/64) words (the h-hop balls at every level and
+ * the per-round change marks).  Returns 0 on invalid arguments. */
+size_t hoTrussWorkspaceBytes(uint32_t n, uint64_t m, uint32_t h, const hoTuning *tune);
+
+/* h-support of every edge in the whole graph, sup_G(e,h) (Def. 3).
+ * out_support[m] (device, uint32) receives the counts in edge-id order. */
+hoStatus hoTrussHSupport(const uint32_t *row_ptr, const uint32_t *col_idx,
+                         uint32_t n, uint64_t m, uint32_t h,
+                         uint32_t *out_support,
+                         void *workspace, size_t workspace_bytes,
+                         const hoTuning *tune, hipStream_t stream);
+
+/* Full decomposition (Section 3, the peeling method): t(e,h) of every edge.
+ * out_trussness[m] (device, uint32) receives t(e,h) >= 2.
+ * out_round[m] (device, uint32, may be NULL) receives the 0-based peel round
+ * of each edge under the bulk schedule: round r removes at once every live
+ * edge with sup <= k-2 at the current level k; rounds that remove nothing
+ * are not counted; k rises to min sup + 2 when nothing qualifies. */
+hoStatus hoTrussDecompose(const uint32_t *row_ptr, const uint32_t *col_idx,
+                          uint32_t n, uint64_t m, uint32_t h,
+                          uint32_t *out_trussness, uint32_t *out_round,
+                          void *workspace, size_t workspace_bytes,
+                          const hoTuning *tune, hipStream_t stream);
+
+/* Counters of the last hoTrussDecompose on this host thread (host pointer). */
+hoStatus hoTrussLastStats(hoStats *out);
+
+/* Many independent graphs in one call.  row_ptr_cat holds graph g's local
+ * (n_g+1)-entry row_ptr at offset vtx_off[g] + g; col_idx_cat holds its local
+ * ids at offset adj_off[g]; its outputs start at edge_off[g].  vtx_off,
+ * adj_off and edge_off are HOST arrays of B+1 entries (prefix sums of n_g,
+ * 2m_g and m_g); h is a HOST array of B hop thresholds.  Results equal B
+ * separate hoTrussDecompose calls (components never interact). */
+size_t hoTrussBatchedWorkspaceBytes(const uint64_t *vtx_off, const uint64_t *edge_off,
+                                    const uint32_t *h, uint32_t B, const hoTuning *tune);
+hoStatus hoTrussDecomposeBatched(const uint32_t *row_ptr_cat, const uint32_t *col_idx_cat,
+                                 const uint64_t *vtx_off, const uint64_t *adj_off,
+                                 const uint64_t *edge_off, const uint32_t *h, uint32_t B,
+                                 uint32_t *out_trussness_cat, uint32_t *out_round_cat,
+                                 void *workspace, size_t workspace_bytes,
+                                 const hoTuning *tune, hipStream_t stream);
+
+const char *hoStatusString(hoStatus s);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* HOTRUSS_H */

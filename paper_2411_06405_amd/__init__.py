@@ -1,0 +1,11 @@
+"""hotruss: higher-order (k,h)-truss decomposition on AMD Instinct MI355X.
+
+The computation lives in libhotruss.so (hand-written HIP kernels for gfx950,
+C ABI declared in include/hotruss.h); this package is its thin Python binding.
+"""
+from ._lib import (HotrussError, Tuning, alloc_workspace, decompose, decompose_graph,
+                   h_support, h_support_graph, last_stats, lib, to_numpy_u32, workspace_bytes)
+
+__all__ = ["HotrussError", "Tuning", "alloc_workspace", "decompose", "decompose_graph",
+           "h_support", "h_support_graph", "last_stats", "lib", "to_numpy_u32",
+           "workspace_bytes"]
