@@ -70,19 +70,29 @@ typedef struct {
     uint32_t event_capacity;  /* per-level ball-change event list entries; a round that
                                  overflows it falls back to full bitset scans (0 = auto)  */
     uint32_t grid_blocks;     /* workgroups of the round driver (0 = auto)               */
+    uint32_t item_capacity;   /* per-level work item list entries; a round that overflows
+                                 it takes the serial path (0 = auto)                      */
 } hoTuning;
 
 #define HO_FLAG_HOST_LOOP 0x1u  /* drive peel rounds from the host, one round per
                                    launch sequence (debugging; slower)                */
-#define HO_FLAG_STATS 0x2u      /* keep per-run counters for hoTrussLastStats          */
+#define HO_FLAG_STATS 0x2u      /* time every kernel with HIP events (implies host loop) */
+#define HO_FLAG_SERIAL_LEVELS 0x4u   /* testing: always take the serial ball-change path */
+#define HO_FLAG_SERIAL_SUPPORT 0x8u  /* testing: always take the serial support path     */
 
 /* Work counters of the last decomposition on this host thread. */
 typedef struct {
     uint64_t rounds;        /* peel rounds that removed at least one edge          */
-    uint64_t levels;        /* distinct levels k visited                           */
+    uint64_t levels;        /* distinct levels k visited (level jumps)             */
     uint64_t events;        /* ball-change events at the top level h               */
-    uint64_t overflows;     /* rounds that fell back to full event scans           */
+    uint64_t overflows;     /* rounds in which a work list overflowed (serial path) */
     double   device_ms;     /* device time of the whole call (HIP events)          */
+    /* HO_FLAG_STATS only: summed HIP-event time and launch count per kernel kind:
+     * 0 initial h-support, 1 level-jump minimum, 2 peel/mark, 3 ball-change
+     * events (all levels), 4 support update, 5 end of round.  Stats mode drives
+     * the rounds from the host, so device_ms is then not the production time. */
+    double   kernel_ms[6];
+    uint64_t kernel_launches[6];
 } hoStats;
 
 /* Bytes of device workspace hoTrussDecompose / hoTrussHSupport need for a

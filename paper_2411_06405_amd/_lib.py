@@ -21,6 +21,8 @@ STATUS = {0: "HO_OK", -1: "HO_ERR_INVALID_ARG", -2: "HO_ERR_BAD_CSR", -3: "HO_ER
           -8: "HO_ERR_NOT_FOUND", -9: "HO_ERR_INTERNAL"}
 HO_FLAG_HOST_LOOP = 0x1
 HO_FLAG_STATS = 0x2
+HO_FLAG_SERIAL_LEVELS = 0x4
+HO_FLAG_SERIAL_SUPPORT = 0x8
 
 
 class HotrussError(RuntimeError):
@@ -32,12 +34,17 @@ class HotrussError(RuntimeError):
 class Tuning(C.Structure):
     _fields_ = [("word_bits", C.c_uint32), ("dense_threshold", C.c_uint32),
                 ("edges_per_wave", C.c_uint32), ("flags", C.c_uint32),
-                ("event_capacity", C.c_uint32), ("grid_blocks", C.c_uint32)]
+                ("event_capacity", C.c_uint32), ("grid_blocks", C.c_uint32),
+                ("item_capacity", C.c_uint32)]
 
 
 class Stats(C.Structure):
     _fields_ = [("rounds", C.c_uint64), ("levels", C.c_uint64), ("events", C.c_uint64),
-                ("overflows", C.c_uint64), ("device_ms", C.c_double)]
+                ("overflows", C.c_uint64), ("device_ms", C.c_double),
+                ("kernel_ms", C.c_double * 6), ("kernel_launches", C.c_uint64 * 6)]
+
+
+KERNEL_KINDS = ("support_init", "jump_min", "mark", "level_events", "support_update", "advance")
 
 
 def _declare(lib):
@@ -148,7 +155,9 @@ def last_stats() -> dict:
     s = Stats()
     _check(lib.hoTrussLastStats(C.byref(s)), "hoTrussLastStats")
     return {"rounds": s.rounds, "levels": s.levels, "events": s.events,
-            "overflows": s.overflows, "device_ms": s.device_ms}
+            "overflows": s.overflows, "device_ms": s.device_ms,
+            "kernel_ms": dict(zip(KERNEL_KINDS, list(s.kernel_ms))),
+            "kernel_launches": dict(zip(KERNEL_KINDS, list(s.kernel_launches)))}
 
 
 def to_numpy_u32(t: torch.Tensor) -> np.ndarray:

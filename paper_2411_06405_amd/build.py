@@ -8,16 +8,25 @@ from pathlib import Path
 PKG = Path(__file__).resolve().parent
 ROOT = PKG.parent
 LIB = PKG / "libhotruss.so"
-SOURCES = [PKG / "csrc" / "hotruss_api.hip"]
+# (source, optimisation level): the serial overflow kernels are built at -O1
+SOURCES = [(PKG / "csrc" / "hotruss_api.hip", "-O3"), (PKG / "csrc" / "hotruss_serial.hip", "-O1")]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
-FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",
+FLAGS = ["--offload-arch=gfx950", "-std=c++17", "-fPIC",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
          "-Wall", "-Wno-unused-function", "-I", str(ROOT / "include")]
 
 
 def build(verbose: bool = False) -> Path:
+    objs = []
+    for src, opt in SOURCES:
+        obj = PKG / "csrc" / (src.stem + ".o")
+        cmd = [HIPCC, *FLAGS, opt, "-c", str(src), "-o", str(obj)]
+        if verbose:
+            print(" ".join(cmd))
+        subprocess.run(cmd, check=True)
+        objs.append(str(obj))
     tmp = LIB.with_suffix(".so.tmp")
-    cmd = [HIPCC, *FLAGS, *map(str, SOURCES), "-o", str(tmp)]
+    cmd = [HIPCC, "--offload-arch=gfx950", "-shared", *objs, "-o", str(tmp)]
     if verbose:
         print(" ".join(cmd))
     subprocess.run(cmd, check=True)

@@ -43,8 +43,8 @@ __global__ void k_init_ctl(Ctl* ctl, uint32_t m) {
     for (uint32_t i = 0; i < sizeof(Ctl) / 4; ++i) w[i] = 0;
     ctl->k = 2;
     ctl->live = m;
-    ctl->minsup = 0xffffffffu;
     ctl->levels = 0;
+    ctl->done = (m == 0);
   }
 }
 
@@ -248,264 +248,478 @@ __global__ void __launch_bounds__(256) k_support_init(Dev d, uint32_t* __restric
   }
 }
 
-// ------------------------------------------------------------ level jump
-__global__ void k_level_min(Dev d) {
-  uint32_t mn = 0xffffffffu;
-  for (uint32_t e = blockIdx.x * blockDim.x + threadIdx.x; e < d.m; e += gridDim.x * blockDim.x)
-    if (d.t[e] == 0) mn = min(mn, d.sup[e]);
-  mn = wave_min(mn);
-  if (lane_id() == 0 && mn != 0xffffffffu) atomicMin(&d.ctl->minsup, mn);
-}
-
-// k <- min sup + 2; R <- live edges with sup <= k-2 (Algorithm 1 moving on
-// to the next non-empty bin).
-__global__ void k_level_collect(Dev d) {
-  const uint32_t k = d.ctl->minsup + 2;
-  const uint32_t p = d.ctl->r & 1;
-  if (blockIdx.x == 0 && threadIdx.x == 0) {
-    d.ctl->k = k;
-    d.ctl->levels += 1;
-  }
-  uint32_t* R = d.R[p];
-  const uint32_t lane = lane_id();
-  const uint32_t nthreads = gridDim.x * blockDim.x;
-  for (uint32_t base = blockIdx.x * blockDim.x + (threadIdx.x & ~(WAVE - 1)); base < d.m;
-       base += nthreads) {
-    const uint32_t e = base + lane;
-    const bool take = e < d.m && d.t[e] == 0 && d.sup[e] + 2 <= k;
-    const uint64_t bal = __ballot(take);
-    if (!bal) continue;
-    uint32_t off = 0;
-    if (lane == 0) off = atomicAdd(&d.ctl->nR, (uint32_t)__popcll(bal));
-    off = __shfl(off, 0, WAVE);
-    if (take) R[off + __popcll(bal & ((1ull << lane) - 1))] = e;
-  }
-}
-
-// ------------------------------------------------------------ peel round
-// Peel R: record t = k and the round, take the edges out of S, record the
-// level-1 events, and clear the previous round's change marks.
-__global__ void k_mark(Dev d) {
-  Ctl* c = d.ctl;
-  const uint32_t r = c->r, k = c->k, nR = c->nR, p = r & 1, q = p ^ 1;
-  const uint32_t* R = d.R[p];
-  const size_t tid = blockIdx.x * (size_t)blockDim.x + threadIdx.x;
-  const size_t nth = (size_t)gridDim.x * blockDim.x;
-  uint64_t* E1 = d.evl[1][p];
-  for (size_t i = tid; i < nR; i += nth) {
-    const uint32_t e = R[i];
-    d.t[e] = k;
-    d.rho[e] = r;
-    d.srem[d.s1[e]] = r;
-    d.srem[d.s2[e]] = r;
-    const uint32_t a = d.eu[e], b = d.ev[e];
-    atomicAnd(&row(d.L[1], d.W, a)[b >> 6], ~(1ull << (b & 63)));
-    atomicAnd(&row(d.L[1], d.W, b)[a >> 6], ~(1ull << (a & 63)));
-    if (d.Dm[1]) {
-      atomicOr(&row(d.Dm[1], d.W, a)[b >> 6], 1ull << (b & 63));
-      atomicOr(&row(d.Dm[1], d.W, b)[a >> 6], 1ull << (a & 63));
-    }
-    E1[2 * i] = ((uint64_t)a << 32) | b;
-    E1[2 * i + 1] = ((uint64_t)b << 32) | a;
-  }
-  if (tid == 0) c->nev[1][p] = 2 * nR;
-  // clear the marks of the previous round (distinct bits from this round's)
-  for (uint32_t j = 1; j <= d.h; ++j) {
-    uint64_t* D = d.Dm[j];
-    if (!D) continue;
-    if (c->ovf[j][q]) {
-      const size_t cnt = (size_t)d.n * d.W;
-      for (size_t i = tid; i < cnt; i += nth) D[i] = 0;
-    } else {
-      const uint32_t ne = c->nev[j][q];
-      const uint64_t* E = d.evl[j][q];
-      for (size_t i = tid; i < ne; i += nth) {
-        const uint64_t xw = E[i];
-        const uint32_t x = (uint32_t)(xw >> 32), w = (uint32_t)xw;
-        atomicAnd(&row(D, d.W, x)[w >> 6], ~(1ull << (w & 63)));
-      }
-    }
-  }
-}
+// ============================================================ peel rounds
+// A round runs as a fixed kernel sequence (captured once into a HIP graph and
+// replayed): k_jump_min, k_mark, k_level(j) for j = 2..h, k_support,
+// k_advance.  Every kernel reads the control block and returns at once when
+// the decomposition is finished, so a graph may run past the last round.
 
 struct RoundCtx {
   uint32_t r, k, p;
 };
 
-// Record that w left x's level-j ball (exactly once, by the thread whose
-// atomic clear found the bit set).
-__device__ __forceinline__ void drop_pair(const Dev& d, uint32_t j, uint32_t p, uint32_t x,
-                                          uint32_t w) {
-  const uint64_t bit = 1ull << (w & 63);
-  const uint64_t old = atomicAnd(&row(d.L[j], d.W, x)[w >> 6], ~bit);
-  if (!(old & bit)) return;
-  atomicOr(&row(d.Dm[j], d.W, x)[w >> 6], bit);
-  const uint32_t idx = atomicAdd(&d.ctl->nev[j][p], 1u);
-  if (idx < d.evcap) d.evl[j][p][idx] = ((uint64_t)x << 32) | w;
-  else d.ctl->ovf[j][p] = 1;
+__device__ __forceinline__ RoundCtx round_ctx(const Ctl* c) { return RoundCtx{c->r, c->k, c->r & 1}; }
+
+// ---- work item emission (all 64 lanes call; per-lane counts may be 0) ----
+// Items over the CSR row of z: nv = deg(z) + extra virtual entries, CHUNK per
+// item; virtual index 0 is the extra candidate when extra = 1.
+__device__ void emit_row_items(const Dev& d, uint32_t list, bool active, uint32_t kind,
+                               uint32_t x, uint32_t y, uint32_t z, uint32_t extra) {
+  uint32_t nch = 0, base = 0, nv = 0;
+  if (active) {
+    base = d.rp[z];
+    nv = d.rp[z + 1] - base + extra;
+    nch = (nv + CHUNK - 1) / CHUNK;
+  }
+  const uint32_t slot = wave_reserve(&d.ctl->nit[list], nch);
+  Item* L = d.itl[list];
+  bool over = false;
+  for (uint32_t c = 0; c < nch; ++c) {
+    const uint32_t idx = slot + c;
+    const uint32_t vs = c * CHUNK;
+    if (idx < d.itcap) L[idx] = Item{x, y, base, item_meta(kind, extra, min(CHUNK, nv - vs), vs)};
+    else over = true;
+  }
+  if (over) d.ctl->iovf[list] = 1;
 }
 
-// Candidate pair (x,w) at level j: if w is still in x's j-ball but no longer
-// within j hops in S_{r+1}, drop the pair in both directions.
-__device__ void test_pair(const Dev& d, uint32_t j, const RoundCtx& rc, uint32_t x, uint32_t w) {
-  if (x == w) return;
-  const uint32_t lo = min(x, w), hi = max(x, w);
-  if (!getbit(d.L[j], d.W, lo, hi)) return;
-  uint32_t a = x, b = w;
-  if (d.rp[a + 1] - d.rp[a] > d.rp[b + 1] - d.rp[b]) { a = w; b = x; }
-  const uint64_t* P = d.L[j - 1];
-  if (getbit(P, d.W, a, b)) return;
-  for (uint32_t q = d.rp[a]; q < d.rp[a + 1]; ++q)
-    if (d.srem[q] > rc.r && getbit(P, d.W, d.ci[q], b)) return;
-  drop_pair(d, j, rc.p, x, w);
-  drop_pair(d, j, rc.p, w, x);
+// Support items of event (a -> w): the live edges (a,b), CHUNK slots per item.
+__device__ void emit_support_items(const Dev& d, bool active, uint32_t a, uint32_t w) {
+  const uint32_t list = d.h + 1;
+  uint32_t nch = 0, base = 0, deg = 0;
+  if (active) {
+    base = d.rp[a];
+    deg = d.rp[a + 1] - base;
+    nch = (deg + CHUNK - 1) / CHUNK;
+  }
+  const uint32_t slot = wave_reserve(&d.ctl->nit[list], nch);
+  Item* L = d.itl[list];
+  bool over = false;
+  for (uint32_t c = 0; c < nch; ++c) {
+    const uint32_t idx = slot + c;
+    if (idx < d.itcap) L[idx] = Item{a, w, base + c * CHUNK, item_meta(0, 0, min(CHUNK, deg - c * CHUNK), 0)};
+    else over = true;
+  }
+  if (over) d.ctl->iovf[list] = 1;
 }
 
-// The wave handles the candidates generated by event (z -> w) at level j-1:
-// (z,w) and (y,w) for every live neighbour y of z.
-__device__ void wave_event_candidates(const Dev& d, uint32_t j, const RoundCtx& rc, uint32_t z,
-                                      uint32_t w) {
-  const uint32_t lane = lane_id();
-  if (lane == 0) test_pair(d, j, rc, z, w);
-  for (uint32_t q = d.rp[z] + lane; q < d.rp[z + 1]; q += WAVE)
-    if (d.srem[q] > rc.r) test_pair(d, j, rc, d.ci[q], w);
+// Items over z's old (j-1)-ball words for candidates (x, w), j >= 3.
+__device__ void emit_word_items(const Dev& d, uint32_t j, bool active, uint32_t x, uint32_t z) {
+  const uint32_t nch = active ? (d.W + CHUNK - 1) / CHUNK : 0;
+  const uint32_t slot = wave_reserve(&d.ctl->nit[j], nch);
+  bool over = false;
+  for (uint32_t c = 0; c < nch; ++c) {
+    const uint32_t idx = slot + c;
+    if (idx < d.itcap)
+      d.itl[j][idx] = Item{x, z, c * CHUNK, item_meta(KIND_A_WORDS, 0, min(CHUNK, d.W - c * CHUNK), 0)};
+    else over = true;
+  }
+  if (over) d.ctl->iovf[j] = 1;
 }
 
-// Level-j events of this round (j >= 2).
-__global__ void __launch_bounds__(256) k_level_events(Dev d, uint32_t j) {
+// Record `cnt` (0..2) events of this lane at level j (all lanes call).
+__device__ void record_events(const Dev& d, uint32_t j, uint32_t p, uint32_t cnt, uint64_t e0,
+                              uint64_t e1) {
+  const uint32_t slot = wave_reserve(&d.ctl->nev[j][p], cnt);
+  const uint32_t cap = (j == 1) ? 2 * d.m + 2 : d.evcap;
+  bool over = false;
+  for (uint32_t i = 0; i < cnt; ++i) {
+    if (slot + i < cap) d.evl[j][p][slot + i] = i ? e1 : e0;
+    else over = true;
+  }
+  if (over) d.ctl->ovf[j][p] = 1;
+}
+
+// ---- K1: level-jump minimum and clearing of overflowed change marks ----
+__global__ void __launch_bounds__(256) k_jump_min(const Dev* __restrict__ dp) {
+  const Dev& d = *dp;
+  __shared__ uint32_t smin[4];
+  const Ctl* c = d.ctl;
+  if (c->done || c->halt) return;
+  const uint32_t p = c->r & 1, q = p ^ 1;
+  if (blockIdx.x == 0 && threadIdx.x == 0) d.ctl->jump = (c->nR == 0);
+  if (c->nR == 0) {
+    uint32_t mn = 0xffffffffu;
+    for (uint32_t e = blockIdx.x * blockDim.x + threadIdx.x; e < d.m; e += gridDim.x * blockDim.x)
+      if (d.t[e] == 0) mn = min(mn, d.sup[e]);
+    mn = wave_min(mn);
+    if (lane_id() == 0) smin[threadIdx.x / WAVE] = mn;
+    __syncthreads();
+    if (threadIdx.x == 0)
+      d.minpart[blockIdx.x] = min(min(smin[0], smin[1]), min(smin[2], smin[3]));
+  }
+  // change marks of a previous round whose event list overflowed
+  for (uint32_t j = 2; j <= d.h; ++j) {
+    if (!c->ovf[j][q]) continue;
+    uint64_t* D = d.Dm[j];
+    const size_t cnt = (size_t)d.n * d.W;
+    for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < cnt;
+         i += (size_t)gridDim.x * blockDim.x)
+      D[i] = 0;
+  }
+}
+
+// ---- K2: peel R (level jump: collect it first), level-1 events, items ----
+__device__ void mark_edge(const Dev& d, const RoundCtx& rc, bool valid, uint32_t e, uint32_t i) {
+  uint32_t a = 0, b = 0;
+  if (valid) {
+    d.t[e] = rc.k;
+    d.rho[e] = rc.r;
+    d.srem[d.s1[e]] = rc.r;
+    d.srem[d.s2[e]] = rc.r;
+    a = d.eu[e];
+    b = d.ev[e];
+    atomicAnd(&row(d.L[1], d.W, a)[b >> 6], ~(1ull << (b & 63)));
+    atomicAnd(&row(d.L[1], d.W, b)[a >> 6], ~(1ull << (a & 63)));
+    if (d.h == 1) {
+      atomicOr(&row(d.Dm[1], d.W, a)[b >> 6], 1ull << (b & 63));
+      atomicOr(&row(d.Dm[1], d.W, b)[a >> 6], 1ull << (a & 63));
+    }
+    d.evl[1][rc.p][2 * i] = ((uint64_t)a << 32) | b;
+    d.evl[1][rc.p][2 * i + 1] = ((uint64_t)b << 32) | a;
+  }
+  if (d.h == 1) {
+    emit_support_items(d, valid, a, b);
+    emit_support_items(d, valid, b, a);
+    return;
+  }
+  // level 2: a lost neighbour b (candidates (a, y), y in b's old neighbourhood,
+  // plus (a, b) itself) and symmetrically; level-1 events (a->b), (b->a):
+  // candidates (y, b), y a live neighbour of a, and symmetrically.
+  emit_row_items(d, 2, valid, KIND_A_SLOTS, a, b, b, 1);
+  emit_row_items(d, 2, valid, KIND_A_SLOTS, b, a, a, 1);
+  emit_row_items(d, 2, valid, KIND_B_SLOTS, a, b, a, 0);
+  emit_row_items(d, 2, valid, KIND_B_SLOTS, b, a, b, 0);
+  for (uint32_t j = 3; j <= d.h; ++j) {
+    emit_word_items(d, j, valid, a, b);
+    emit_word_items(d, j, valid, b, a);
+  }
+}
+
+__global__ void __launch_bounds__(256) k_mark(const Dev* __restrict__ dp) {
+  const Dev& d = *dp;
   Ctl* c = d.ctl;
-  RoundCtx rc{c->r, c->k, c->r & 1};
-  const uint32_t nR = c->nR;
-  const uint32_t A = 2 * nR;
-  const bool scan = c->ovf[j - 1][rc.p] != 0;
-  // level-1 lists always hold every event (2|R| entries); deeper lists may overflow
-  const uint32_t Bn = scan ? d.n : (j - 1 == 1 ? c->nev[1][rc.p] : min(c->nev[j - 1][rc.p], d.evcap));
+  if (c->done || c->halt) return;
+  RoundCtx rc = round_ctx(c);
+  const uint32_t q = rc.p ^ 1;
   const uint32_t lane = lane_id();
-  const uint32_t wpb = blockDim.x / WAVE;
-  const uint64_t total = (uint64_t)A + Bn;
-  for (uint64_t it = blockIdx.x * wpb + threadIdx.x / WAVE; it < total;
-       it += (uint64_t)gridDim.x * wpb) {
-    if (it < A) {
-      // x lost its neighbour z: candidates w in z's old (j-1)-ball
-      const uint32_t e = d.R[rc.p][it >> 1];
-      const bool o = it & 1;
-      const uint32_t x = o ? d.ev[e] : d.eu[e];
-      const uint32_t z = o ? d.eu[e] : d.ev[e];
-      if (j == 2) {
-        if (lane == 0) test_pair(d, j, rc, x, z);
-        for (uint32_t q = d.rp[z] + lane; q < d.rp[z + 1]; q += WAVE)
-          if (d.srem[q] >= rc.r) test_pair(d, j, rc, x, d.ci[q]);
+  const uint32_t wstride = gridDim.x * blockDim.x;
+  const uint32_t wbase = blockIdx.x * blockDim.x + (threadIdx.x & ~(WAVE - 1));
+  if (c->jump) {
+    // level jump: k <- min live sup + 2 (Algorithm 1 moving to the next
+    // non-empty bin); R <- every live edge with sup <= k-2
+    uint32_t mn = 0xffffffffu;
+    for (uint32_t i = lane; i < d.nminpart; i += WAVE) mn = min(mn, d.minpart[i]);
+    mn = wave_min(mn);
+    rc.k = mn + 2;
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+      c->k = rc.k;
+      c->levels += 1;
+    }
+    for (uint32_t base = wbase; base < d.m; base += wstride) {
+      const uint32_t e = base + lane;
+      const bool take = e < d.m && d.t[e] == 0 && d.sup[e] + 2 <= rc.k;
+      const uint32_t i = wave_reserve(&c->nR, take ? 1u : 0u);
+      if (take) d.R[rc.p][i] = e;
+      mark_edge(d, rc, take, e, i);
+    }
+  } else {
+    const uint32_t nR = c->nR;
+    for (uint32_t base = wbase; base < nR; base += wstride) {
+      const uint32_t i = base + lane;
+      const bool valid = i < nR;
+      mark_edge(d, rc, valid, valid ? d.R[rc.p][i] : 0, i);
+    }
+  }
+  // clear the listed change marks of the previous round (distinct bits from
+  // the ones this round sets); overflowed levels were cleared by k_jump_min
+  for (uint32_t j = 1; j <= d.h; ++j) {
+    uint64_t* D = d.Dm[j];
+    if (!D || c->ovf[j][q]) continue;
+    const uint32_t ne = c->nev[j][q];
+    const uint64_t* E = d.evl[j][q];
+    for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < ne; i += wstride) {
+      const uint64_t xw = E[i];
+      const uint32_t x = (uint32_t)(xw >> 32), w = (uint32_t)xw;
+      atomicAnd(&row(D, d.W, x)[w >> 6], ~(1ull << (w & 63)));
+    }
+  }
+}
+
+// ---- K3: ball-change events at level j >= 2 ----------------------------
+constexpr uint32_t LV_THREADS = 256;
+constexpr uint32_t LV_WAVES = LV_THREADS / WAVE;
+constexpr uint32_t LV_CAP = 1024;  // candidate pairs buffered per workgroup
+
+// Block-wide exclusive scan of v[0..n) (n <= LV_CAP) into out; returns the total.
+__device__ uint32_t block_scan_cap(const uint32_t* v, uint32_t* out, uint32_t n, uint32_t* wsum) {
+  const uint32_t per = LV_CAP / LV_THREADS;  // 4 entries per thread
+  const uint32_t b0 = threadIdx.x * per;
+  uint32_t loc[per];
+  uint32_t s = 0;
+  for (uint32_t i = 0; i < per; ++i) {
+    loc[i] = (b0 + i < n) ? v[b0 + i] : 0u;
+    s += loc[i];
+  }
+  uint32_t wtot;
+  const uint32_t wex = wave_excl_scan(s, &wtot);
+  if (lane_id() == 0) wsum[threadIdx.x / WAVE] = wtot;
+  __syncthreads();
+  uint32_t off = 0, tot = 0;
+  for (uint32_t w = 0; w < LV_WAVES; ++w) {
+    if (w < threadIdx.x / WAVE) off += wsum[w];
+    tot += wsum[w];
+  }
+  uint32_t run = off + wex;
+  for (uint32_t i = 0; i < per; ++i) {
+    if (b0 + i < n) out[b0 + i] = run;
+    run += loc[i];
+  }
+  __syncthreads();
+  return tot;
+}
+
+// Level-j events.  Each workgroup turns its share of work items into
+// candidate pairs (quick filters: still in the j-ball, not directly
+// reachable), buffers them in LDS, then tests every buffered pair at once:
+// the pair's probes (the live neighbours y of its lower-degree endpoint a,
+// each checked against the other endpoint's (j-1)-ball) are laid out flat
+// over all threads of the workgroup.  Pairs with no witness leave the ball.
+__global__ void __launch_bounds__(LV_THREADS) k_level(const Dev* __restrict__ dp, uint32_t j) {
+  const Dev& d = *dp;
+  __shared__ uint32_t cx[LV_CAP], cw[LV_CAP], cb[LV_CAP], cbeg[LV_CAP], cdeg[LV_CAP],
+      coff[LV_CAP];
+  __shared__ uint32_t cflag[LV_CAP];
+  __shared__ uint32_t s_count, s_busy[2], s_wsum[LV_WAVES];
+  Ctl* c = d.ctl;
+  if (c->done) return;
+  if (c->halt) return;
+  if (c->iovf[j] || (d.serial & 4u)) {
+    // work list overflowed: leave this level to the serial kernel the host runs
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+      c->halt = 1;
+      c->halt_step = j;
+    }
+    return;
+  }
+  const RoundCtx rc = round_ctx(c);
+  const uint32_t nit = min(c->nit[j], d.itcap);
+  const uint32_t wave = threadIdx.x / WAVE, lane = lane_id();
+  const uint32_t stride = gridDim.x * LV_WAVES;
+  uint32_t it = blockIdx.x * LV_WAVES + wave;
+  if (blockIdx.x * LV_WAVES >= nit) return;  // whole workgroup idle
+  const uint64_t* Lj = d.L[j];
+  const uint64_t* Lp = d.L[j - 1];
+  const Item* items = d.itl[j];
+  if (threadIdx.x == 0) {
+    s_count = 0;
+    s_busy[0] = s_busy[1] = 0;
+  }
+  for (uint32_t i = threadIdx.x; i < LV_CAP; i += LV_THREADS) cflag[i] = 0;
+  uint32_t par = 0;
+  uint64_t wd = 0;       // KIND_A_WORDS: this lane's remaining ball word
+  bool inword = false;   // KIND_A_WORDS item in progress
+  __syncthreads();
+  while (true) {
+    // ---- one emission step per wave: at most one candidate per lane ----
+    bool have = false;
+    uint32_t X = 0, Wv = 0;
+    if (it < nit) {
+      const Item I = items[it];
+      const uint32_t kind = meta_kind(I.meta), len = meta_len(I.meta);
+      if (kind == KIND_A_WORDS) {
+        if (!inword) {
+          wd = 0;
+          if (lane < len) {
+            const size_t o = (size_t)I.y * d.W + I.base + lane;
+            wd = d.L[j - 1][o] | d.Dm[j - 1][o];
+          }
+          inword = true;
+        }
+        if (wd) {
+          const uint32_t b = __ffsll((unsigned long long)wd) - 1;
+          wd &= wd - 1;
+          have = true;
+          X = I.x;
+          Wv = (I.base + lane) * 64 + b;
+        }
+        if (!__ballot(wd != 0)) {
+          inword = false;
+          it += stride;
+        }
       } else {
-        const uint64_t* Lp = row(d.L[j - 1], d.W, z);
-        const uint64_t* Dp = row(d.Dm[j - 1], d.W, z);
-        for (uint32_t i = lane; i < d.W; i += WAVE) {
-          uint64_t wd = Lp[i] | Dp[i];
-          while (wd) {
-            const uint32_t b = __ffsll((unsigned long long)wd) - 1;
-            wd &= wd - 1;
-            test_pair(d, j, rc, x, i * 64 + b);
+        const uint32_t extra = meta_extra(I.meta);
+        const uint32_t v = meta_vstart(I.meta) + lane;
+        if (lane < len) {
+          if (extra && v == 0) {
+            have = true;
+            X = I.x;
+            Wv = I.y;
+          } else {
+            const uint32_t q = I.base + v - extra;
+            const uint32_t sr = d.srem[q];
+            if (kind == KIND_A_SLOTS ? sr >= rc.r : sr > rc.r) {
+              have = true;
+              const uint32_t y2 = d.ci[q];
+              X = (kind == KIND_A_SLOTS) ? I.x : y2;
+              Wv = (kind == KIND_A_SLOTS) ? y2 : I.y;
+            }
           }
         }
-      }
-    } else if (!scan) {
-      const uint64_t zw = d.evl[j - 1][rc.p][it - A];
-      wave_event_candidates(d, j, rc, (uint32_t)(zw >> 32), (uint32_t)zw);
-    } else {
-      // event list overflowed: enumerate row z of the change marks
-      const uint32_t z = (uint32_t)(it - A);
-      const uint64_t* Dp = row(d.Dm[j - 1], d.W, z);
-      for (uint32_t i0 = 0; i0 < d.W; i0 += WAVE) {
-        const uint64_t wd = (i0 + lane < d.W) ? Dp[i0 + lane] : 0ull;
-        uint64_t nz = __ballot(wd != 0);
-        while (nz) {
-          const uint32_t src = __ffsll((unsigned long long)nz) - 1;
-          nz &= nz - 1;
-          uint64_t bits = __shfl(wd, src, WAVE);
-          while (bits) {
-            const uint32_t b = __ffsll((unsigned long long)bits) - 1;
-            bits &= bits - 1;
-            wave_event_candidates(d, j, rc, z, (i0 + src) * 64 + b);
-          }
-        }
+        it += stride;
       }
     }
+    // quick filters: a real pair, still in the j-ball, not within j-1 hops
+    uint32_t a = 0, b = 0, beg = 0, deg = 0;
+    if (have) {
+      have = X != Wv && getbit(Lj, d.W, min(X, Wv), max(X, Wv));
+      if (have) {
+        const uint32_t bx = d.rp[X], dx = d.rp[X + 1] - bx;
+        const uint32_t bw = d.rp[Wv], dw = d.rp[Wv + 1] - bw;
+        a = dx <= dw ? X : Wv;
+        b = dx <= dw ? Wv : X;
+        beg = dx <= dw ? bx : bw;
+        deg = dx <= dw ? dx : dw;
+        have = !getbit(Lp, d.W, a, b);
+      }
+    }
+    const uint64_t bal = __ballot(have);
+    uint32_t slot = 0;
+    if (lane == 0 && bal) slot = atomicAdd(&s_count, (uint32_t)__popcll(bal));
+    slot = __shfl(slot, 0, WAVE) + (uint32_t)__popcll(bal & ((1ull << lane) - 1));
+    if (have) {
+      cx[slot] = X;
+      cw[slot] = Wv;
+      cb[slot] = b;
+      cbeg[slot] = beg;
+      cdeg[slot] = deg;
+    }
+    __syncthreads();  // appends visible
+    if (lane == 0 && (it < nit || inword)) atomicOr(&s_busy[par], 1u);
+    __syncthreads();  // flags visible
+    const bool busy = s_busy[par] != 0;
+    const uint32_t n = s_count;
+    __syncthreads();  // everyone has read both before anyone changes them
+    if (threadIdx.x == 0) s_busy[par ^ 1] = 0;
+    par ^= 1;
+    if (n == 0 && !busy) break;
+    if (n + LV_THREADS <= LV_CAP && busy) continue;
+    // ---- flush: probe every buffered pair ----
+    const uint32_t total = block_scan_cap(cdeg, coff, n, s_wsum);
+    for (uint32_t pidx = threadIdx.x; pidx < total; pidx += LV_THREADS) {
+      uint32_t lo = 0, hi = n;
+      while (hi - lo > 1) {
+        const uint32_t mid = (lo + hi) >> 1;
+        if (coff[mid] <= pidx) lo = mid; else hi = mid;
+      }
+      if (cflag[lo]) continue;
+      const uint32_t q = cbeg[lo] + (pidx - coff[lo]);
+      if (d.srem[q] > rc.r && getbit(Lp, d.W, cb[lo], d.ci[q])) cflag[lo] = 1;
+    }
+    __syncthreads();
+    // ---- pairs without a witness leave the j-ball (both directions) ----
+    for (uint32_t base = 0; base < n; base += LV_THREADS) {
+      const uint32_t i = base + threadIdx.x;
+      const bool drop = i < n && !cflag[i];
+      uint32_t x = 0, w = 0;
+      bool w1 = false, w2 = false;
+      if (drop) {
+        x = cx[i];
+        w = cw[i];
+        const uint64_t bx = 1ull << (w & 63), bw = 1ull << (x & 63);
+        w1 = atomicAnd(&row(d.L[j], d.W, x)[w >> 6], ~bx) & bx;
+        w2 = atomicAnd(&row(d.L[j], d.W, w)[x >> 6], ~bw) & bw;
+        if (w1) atomicOr(&row(d.Dm[j], d.W, x)[w >> 6], bx);
+        if (w2) atomicOr(&row(d.Dm[j], d.W, w)[x >> 6], bw);
+      }
+      const uint64_t exw = ((uint64_t)x << 32) | w, ewx = ((uint64_t)w << 32) | x;
+      record_events(d, j, rc.p, (uint32_t)w1 + (uint32_t)w2, w1 ? exw : ewx, ewx);
+      if (j == d.h) {
+        emit_support_items(d, w1, x, w);
+        emit_support_items(d, w2, w, x);
+      } else {
+        emit_row_items(d, j + 1, w1, KIND_B_SLOTS, x, w, x, 1);
+        emit_row_items(d, j + 1, w2, KIND_B_SLOTS, w, x, w, 1);
+      }
+    }
+    __syncthreads();
+    for (uint32_t i = threadIdx.x; i < n; i += LV_THREADS) cflag[i] = 0;
+    if (threadIdx.x == 0) s_count = 0;
+    __syncthreads();
+    if (!busy) break;
   }
 }
 
-// Top-level event (a -> w): charge every live edge (a,b) that had w as a
-// common h-neighbour (see the header comment for the old/new rule).
-__device__ void wave_support_event(const Dev& d, const RoundCtx& rc, uint32_t a, uint32_t w,
-                                   uint32_t* Rn) {
-  const uint32_t lane = lane_id();
-  const uint64_t* Lw = row(d.L[d.h], d.W, w);
-  const uint64_t* Dw = row(d.Dm[d.h], d.W, w);
-  for (uint32_t q = d.rp[a] + lane; q < d.rp[a + 1]; q += WAVE) {
-    if (d.srem[q] <= rc.r) continue;
-    const uint32_t b = d.ci[q];
-    uint64_t word = Lw[b >> 6];
-    if (a < b) word |= Dw[b >> 6];
-    if (!((word >> (b & 63)) & 1ull)) continue;
-    const uint32_t e = d.eid[q];
-    const uint32_t old = atomicSub(&d.sup[e], 1u);
-    if (old == rc.k - 1) {
-      const uint32_t idx = atomicAdd(&d.ctl->nPush, 1u);
-      Rn[idx] = e;
-    }
-  }
-}
-
-__global__ void __launch_bounds__(256) k_support_update(Dev d) {
+// ---- K4: support update --------------------------------------------------
+// Top-level event (a -> w): every live edge (a,b) that had w as a common
+// h-neighbour loses it.  Old/new rule: w counts against (a,b) if it was in
+// b's old ball when a < b, and in b's new ball when a > b (see the header).
+__global__ void __launch_bounds__(256) k_support(const Dev* __restrict__ dp) {
+  const Dev& d = *dp;
   Ctl* c = d.ctl;
-  RoundCtx rc{c->r, c->k, c->r & 1};
-  const uint32_t h = d.h;
-  const bool scan = c->ovf[h][rc.p] != 0;
-  const uint32_t total = scan ? d.n : min(c->nev[h][rc.p], h == 1 ? 2 * d.m : d.evcap);
+  if (c->done) return;
+  const uint32_t list = d.h + 1;
+  if (c->halt) return;
+  if (c->iovf[list] || (d.serial & 8u)) {
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+      c->halt = 1;
+      c->halt_step = list;
+    }
+    return;
+  }
+  const RoundCtx rc = round_ctx(c);
+  const uint32_t nit = min(c->nit[list], d.itcap);
+  const uint32_t lane = lane_id(), wpb = blockDim.x / WAVE;
+  const uint64_t* Lh = d.L[d.h];
+  const uint64_t* Dh = d.Dm[d.h];
   uint32_t* Rn = d.R[rc.p ^ 1];
-  const uint32_t lane = lane_id();
-  const uint32_t wpb = blockDim.x / WAVE;
-  for (uint32_t it = blockIdx.x * wpb + threadIdx.x / WAVE; it < total; it += gridDim.x * wpb) {
-    if (!scan) {
-      const uint64_t aw = d.evl[h][rc.p][it];
-      wave_support_event(d, rc, (uint32_t)(aw >> 32), (uint32_t)aw, Rn);
-    } else {
-      const uint32_t a = it;
-      const uint64_t* Dp = row(d.Dm[h], d.W, a);
-      for (uint32_t i0 = 0; i0 < d.W; i0 += WAVE) {
-        const uint64_t wd = (i0 + lane < d.W) ? Dp[i0 + lane] : 0ull;
-        uint64_t nz = __ballot(wd != 0);
-        while (nz) {
-          const uint32_t src = __ffsll((unsigned long long)nz) - 1;
-          nz &= nz - 1;
-          uint64_t bits = __shfl(wd, src, WAVE);
-          while (bits) {
-            const uint32_t b = __ffsll((unsigned long long)bits) - 1;
-            bits &= bits - 1;
-            wave_support_event(d, rc, a, (i0 + src) * 64 + b, Rn);
-          }
-        }
+  for (uint32_t it = blockIdx.x * wpb + threadIdx.x / WAVE; it < nit; it += gridDim.x * wpb) {
+    const Item I = d.itl[list][it];
+    const uint32_t len = meta_len(I.meta);
+    bool push = false;
+    uint32_t e = 0;
+    if (lane < len) {
+      const uint32_t q = I.base + lane;
+      if (d.srem[q] > rc.r) {
+        const uint32_t b = d.ci[q];
+        e = d.eid[q];
+        const size_t o = (size_t)I.y * d.W + (b >> 6);
+        uint64_t word = Lh[o];
+        if (I.x < b) word |= Dh[o];
+        if ((word >> (b & 63)) & 1ull) push = atomicSub(&d.sup[e], 1u) == rc.k - 1;
       }
     }
+    const uint32_t slot = wave_reserve(&c->nPush, push ? 1u : 0u);
+    if (push) Rn[slot] = e;
   }
 }
 
-// End of round: bookkeeping by one thread.
-__global__ void k_advance(Dev d) {
+// ---- K5: end of round ------------------------------------------------------
+__global__ void k_advance(const Dev* __restrict__ dp) {
+  const Dev& d = *dp;
   if (blockIdx.x != 0 || threadIdx.x != 0) return;
   Ctl* c = d.ctl;
+  if (c->done || c->halt) return;
   const uint32_t p = c->r & 1, q = p ^ 1;
+  c->nev[1][p] = 2 * c->nR;  // level-1 events: both directions of every peeled edge
   c->events += c->nev[d.h][p];
+  c->jump = 0;
   uint32_t any = 0;
   for (uint32_t j = 1; j <= d.h; ++j) {
     any |= c->ovf[j][p];
     c->nev[j][q] = 0;
     c->ovf[j][q] = 0;
   }
+  for (uint32_t j = 0; j <= d.h + 1; ++j) {
+    any |= c->iovf[j];
+    c->nit[j] = 0;
+    c->iovf[j] = 0;
+  }
   c->overflows += any ? 1 : 0;
   c->live -= c->nR;
   c->r += 1;
   c->nR = c->nPush;
   c->nPush = 0;
-  c->minsup = 0xffffffffu;
   if (c->live == 0) c->done = 1;
 }
 

@@ -60,7 +60,7 @@ def test_event_overflow_fallback_exact():
     # a tiny event list forces the full-scan fallback in most rounds
     g = W.d1(2)
     for h in (2, 3):
-        t, rho = run_gpu(g, h, tune={"event_capacity": 8})
+        t, rho = run_gpu(g, h, tune={"event_capacity": 8, "item_capacity": 8})
         to, ro, _ = oracle.decompose(g, h)
         assert np.array_equal(t, to) and np.array_equal(rho, ro)
 
@@ -94,3 +94,53 @@ def test_deterministic():
     a = run_gpu(g, 2)
     b = run_gpu(g, 2)
     assert np.array_equal(a[0], b[0]) and np.array_equal(a[1], b[1])
+
+
+@pytest.mark.parametrize("h", [2, 3])
+def test_overflow_fallback_small_graph_exact(h):
+    # capacities of a few entries force the serial fallback in nearly every round
+    g = W.d2(n=1500)
+    for cap in (4, 256):
+        t, rho = run_gpu(g, h, tune={"event_capacity": cap, "item_capacity": cap})
+        to, ro, _ = oracle.decompose(g, h)
+        assert np.array_equal(t, to) and np.array_equal(rho, ro), cap
+
+
+@pytest.mark.parametrize("make", [lambda: W.d2(n=20000), lambda: W.d3(scale=11)])
+def test_overflow_fallback_at_scale(make):
+    # rows of hundreds of bitset words: the fallback must agree with the
+    # work-list path in every round, whichever of the two a round takes
+    import paper_2411_06405_amd as ht
+    g = make()
+    ref_t, ref_r = run_gpu(g, 2, tune={"event_capacity": 1 << 26, "item_capacity": 1 << 26})
+    assert ht.last_stats()["overflows"] == 0
+    for cap in (4096, 65536):
+        t, rho = run_gpu(g, 2, tune={"event_capacity": cap, "item_capacity": cap})
+        assert ht.last_stats()["overflows"] > 0
+        assert np.array_equal(t, ref_t) and np.array_equal(rho, ref_r), cap
+
+
+@pytest.mark.parametrize("h", [2, 3])
+def test_forced_serial_paths_exact(h):
+    # each serial step alone, both together, and overflowing lists
+    import paper_2411_06405_amd as ht
+    L, S = ht._lib.HO_FLAG_SERIAL_LEVELS, ht._lib.HO_FLAG_SERIAL_SUPPORT
+    g = W.d2(n=1500) if h == 2 else W.d2(n=1000)
+    to, ro, _ = oracle.decompose(g, h)
+    for tune in ({"flags": L}, {"flags": S}, {"flags": L | S}, {"item_capacity": 4},
+                 {"event_capacity": 4}, {"item_capacity": 64, "event_capacity": 64}):
+        t, rho = run_gpu(g, h, tune=tune)
+        assert np.array_equal(t, to) and np.array_equal(rho, ro), tune
+
+
+def test_host_loop_equals_graph():
+    import paper_2411_06405_amd as ht
+    g = W.d2(n=5000)
+    a = run_gpu(g, 2)
+    b = run_gpu(g, 2, tune={"flags": ht._lib.HO_FLAG_HOST_LOOP})
+    c = run_gpu(g, 2, tune={"flags": ht._lib.HO_FLAG_STATS})
+    st = ht.last_stats()
+    assert st["kernel_launches"]["support_update"] == st["rounds"]
+    assert st["kernel_ms"]["support_update"] > 0
+    for x in (b, c):
+        assert np.array_equal(a[0], x[0]) and np.array_equal(a[1], x[1])
