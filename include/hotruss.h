@@ -93,6 +93,11 @@ typedef struct {
      * the rounds from the host, so device_ms is then not the production time. */
     double   kernel_ms[6];
     uint64_t kernel_launches[6];
+    /* HO_FLAG_STATS only: work done by the chunked kernels.  Ball-change
+     * events: [0] work items, [1] candidate slots examined, [2] candidate pairs
+     * tested, [3] witness probes, [4] pairs dropped (directed events).  Support
+     * update: [5] work items, [6] adjacency slots, [7] common h-neighbours lost. */
+    uint64_t work[8];
 } hoStats;
 
 /* Bytes of device workspace hoTrussDecompose / hoTrussHSupport need for a

@@ -41,10 +41,13 @@ class Tuning(C.Structure):
 class Stats(C.Structure):
     _fields_ = [("rounds", C.c_uint64), ("levels", C.c_uint64), ("events", C.c_uint64),
                 ("overflows", C.c_uint64), ("device_ms", C.c_double),
-                ("kernel_ms", C.c_double * 6), ("kernel_launches", C.c_uint64 * 6)]
+                ("kernel_ms", C.c_double * 6), ("kernel_launches", C.c_uint64 * 6),
+                ("work", C.c_uint64 * 8)]
 
 
 KERNEL_KINDS = ("support_init", "jump_min", "mark", "level_events", "support_update", "advance")
+WORK_KINDS = ("level_items", "level_slots", "level_candidates", "level_probes", "level_drops",
+              "support_items", "support_slots", "support_hits")
 
 
 def _declare(lib):
@@ -157,7 +160,8 @@ def last_stats() -> dict:
     return {"rounds": s.rounds, "levels": s.levels, "events": s.events,
             "overflows": s.overflows, "device_ms": s.device_ms,
             "kernel_ms": dict(zip(KERNEL_KINDS, list(s.kernel_ms))),
-            "kernel_launches": dict(zip(KERNEL_KINDS, list(s.kernel_launches)))}
+            "kernel_launches": dict(zip(KERNEL_KINDS, list(s.kernel_launches))),
+            "work": dict(zip(WORK_KINDS, list(s.work)))}
 
 
 def to_numpy_u32(t: torch.Tensor) -> np.ndarray:

@@ -29,7 +29,7 @@ struct Plan {
   uint64_t m = 0;
   bool full = true;  // decomposition (false: support only)
   size_t off_ctl, off_eid, off_eu, off_ev, off_s1, off_s2, off_srem, off_upcnt, off_upoff,
-      off_scan, off_minpart, off_dev, off_sup, off_rho, off_R0, off_R1, off_L[HMAX + 1],
+      off_scan, off_minpart, off_dev, off_spart, off_sup, off_rho, off_R0, off_R1, off_L[HMAX + 1],
       off_Dm[HMAX + 1], off_evl[HMAX + 1][2], off_itl[HMAX + 2];
   size_t total = 0;
 };
@@ -51,10 +51,12 @@ bool make_plan(uint32_t n, uint64_t m, uint32_t h, const hoTuning* tune, bool fu
   Plan p;
   p.n = n; p.m = m; p.h = h; p.full = full;
   p.W = words_per_row(n);
+  // Lists are sized so that a round rarely overflows them (a round that does
+  // runs its level or support step through the serial kernels, far slower).
   p.evcap = tune && tune->event_capacity ? tune->event_capacity
-                                         : clamp_cap(16 * m, 1u << 20, 1u << 27);
+                                         : clamp_cap(128 * m, 1u << 20, 1u << 27);
   p.itcap = tune && tune->item_capacity ? tune->item_capacity
-                                        : clamp_cap(16 * m, 1u << 20, 1u << 26);
+                                        : clamp_cap(128 * m, 1u << 20, 1u << 27);
   const size_t rowbytes = (size_t)p.W * 8;
   if (rowbytes > MAX_LDS_ROW) return false;  // rows are built in LDS
   size_t o = 0;
@@ -71,6 +73,7 @@ bool make_plan(uint32_t n, uint64_t m, uint32_t h, const hoTuning* tune, bool fu
   p.off_scan = take(4 * ((size_t)n / 1024 + 2));
   p.off_minpart = take(4 * MIN_PART);
   p.off_dev = take(sizeof(Dev));
+  p.off_spart = take(4ull * NSTAT * STAT_GRID);
   p.off_sup = take(4 * m + 4);
   p.off_rho = take(full ? 4 * m + 4 : 0);
   p.off_R0 = take(full ? 4 * m + 4 : 0);
@@ -118,6 +121,8 @@ unsigned grid_for(size_t items, unsigned per_block, unsigned cap_mult = 16) {
   return (unsigned)g;
 }
 
+thread_local uint32_t* stats_part_base = nullptr;  // workspace slot of the stats counters
+
 Dev carve(const Plan& p, void* ws, const uint32_t* rp, const uint32_t* ci, uint32_t* t,
           uint32_t* rho) {
   uintptr_t base = ((uintptr_t)ws + ALIGN - 1) / ALIGN * ALIGN;
@@ -143,6 +148,8 @@ Dev carve(const Plan& p, void* ws, const uint32_t* rp, const uint32_t* ci, uint3
   d.minpart = (uint32_t*)at(p.off_minpart);
   d.self = (Dev*)at(p.off_dev);
   d.serial = 0;
+  d.spart = nullptr;  // set in stats mode
+  stats_part_base = (uint32_t*)at(p.off_spart);
   d.sup = (uint32_t*)at(p.off_sup);
   d.t = t;
   d.rho = rho ? rho : (p.full ? (uint32_t*)at(p.off_rho) : nullptr);
@@ -319,6 +326,10 @@ hoStatus steps_host(const Dev& d, const RoundGrid& g, hipStream_t s, uint32_t fr
       if (step <= d.h) hipLaunchKernelGGL(k_level, dim3(g.level), dim3(LV_THREADS), 0, s, dp, step);
       else hipLaunchKernelGGL(k_support, dim3(g.support), dim3(T), 0, s, dp);
       HOCHK(tm.end(s, step <= d.h ? KT_LEVEL : KT_SUPPORT));
+      if (d.spart) {
+        if (step <= d.h) hipLaunchKernelGGL(k_stats_fold, dim3(1), dim3(256), 0, s, dp, 0u, 5u, g.level);
+        else hipLaunchKernelGGL(k_stats_fold, dim3(1), dim3(256), 0, s, dp, 5u, 3u, g.support);
+      }
       hoStatus st = read_ctl(d, &c, s);
       if (st != HO_OK) return st;
       serial = c.halt != 0;
@@ -506,6 +517,10 @@ hoStatus hoTrussDecompose(const uint32_t* row_ptr, const uint32_t* col_idx, uint
   Dev d = carve(p, workspace, row_ptr, col_idx, out_trussness, out_round);
   if (tune) d.serial = tune->flags & (HO_FLAG_SERIAL_LEVELS | HO_FLAG_SERIAL_SUPPORT);
   const bool stats = tune && (tune->flags & HO_FLAG_STATS);
+  if (stats) {
+    d.spart = stats_part_base;
+    HIPCHK(hipMemsetAsync(d.spart, 0, 4ull * NSTAT * STAT_GRID, stream));
+  }
   const bool host_loop = stats || (tune && (tune->flags & HO_FLAG_HOST_LOOP));
   hoStats out{};
   hipEvent_t ev0, ev1, es0 = nullptr, es1 = nullptr;
@@ -555,6 +570,7 @@ hoStatus hoTrussDecompose(const uint32_t* row_ptr, const uint32_t* col_idx, uint
   out.events = c.events;
   out.overflows = c.overflows;
   out.device_ms = ms;
+  for (uint32_t i = 0; i < NSTAT; ++i) out.work[i] = c.stat[i];
   t_stats = out;
   return HO_OK;
 }

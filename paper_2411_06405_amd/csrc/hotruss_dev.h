@@ -11,6 +11,8 @@ constexpr uint32_t ALIVE = 0xffffffffu;  // srem value of a slot whose edge is s
 constexpr int WAVE = 64;
 constexpr uint32_t CHUNK = 64;           // slots (or bitset words) per work item
 constexpr uint32_t MIN_PART = 1024;      // partial-minimum slots of the level-jump reduction
+constexpr uint32_t NSTAT = 8;            // work counters kept in stats mode
+constexpr uint32_t STAT_GRID = 8192;     // most workgroups a counted kernel may use
 
 // error bits in Ctl::err (set by the validation kernels)
 constexpr uint32_t ERR_ROWPTR = 1u, ERR_COL = 2u, ERR_ORDER = 4u, ERR_LOOP = 8u,
@@ -61,6 +63,8 @@ struct Ctl {
   uint32_t nit[HMAX + 2];     // work items per level (index h+1: support items)
   uint32_t iovf[HMAX + 2];    // work item list overflowed
   uint32_t pad[7];
+  // stats mode: work counters, level kernel [0..5), support kernel [5..8)
+  uint64_t stat[NSTAT];
 };
 
 // Everything a kernel needs, passed by value.
@@ -93,6 +97,7 @@ struct Dev {
   Item* itl[HMAX + 2];     // work items per level; index h+1: support items
   Ctl* ctl;
   Dev* self;               // device-resident copy of this struct (round kernels read it)
+  uint32_t* spart;         // stats mode: per-workgroup counters [NSTAT][STAT_GRID], else null
 };
 
 __device__ __forceinline__ uint32_t lane_id() { return threadIdx.x & (WAVE - 1); }

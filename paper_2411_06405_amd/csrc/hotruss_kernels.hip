@@ -491,6 +491,7 @@ __global__ void __launch_bounds__(LV_THREADS) k_level(const Dev* __restrict__ dp
       coff[LV_CAP];
   __shared__ uint32_t cflag[LV_CAP];
   __shared__ uint32_t s_count, s_busy[2], s_wsum[LV_WAVES];
+  __shared__ uint32_t s_stat[5];  // stats mode: items, slots, candidates, probes, drops
   Ctl* c = d.ctl;
   if (c->done) return;
   if (c->halt) return;
@@ -507,7 +508,12 @@ __global__ void __launch_bounds__(LV_THREADS) k_level(const Dev* __restrict__ dp
   const uint32_t wave = threadIdx.x / WAVE, lane = lane_id();
   const uint32_t stride = gridDim.x * LV_WAVES;
   uint32_t it = blockIdx.x * LV_WAVES + wave;
-  if (blockIdx.x * LV_WAVES >= nit) return;  // whole workgroup idle
+  const bool counting = d.spart != nullptr;
+  if (counting && threadIdx.x < 5) s_stat[threadIdx.x] = 0;
+  if (blockIdx.x * LV_WAVES >= nit) {  // whole workgroup idle
+    if (counting && threadIdx.x < 5) d.spart[threadIdx.x * STAT_GRID + blockIdx.x] = 0;
+    return;
+  }
   const uint64_t* Lj = d.L[j];
   const uint64_t* Lp = d.L[j - 1];
   const Item* items = d.itl[j];
@@ -522,7 +528,7 @@ __global__ void __launch_bounds__(LV_THREADS) k_level(const Dev* __restrict__ dp
   __syncthreads();
   while (true) {
     // ---- one emission step per wave: at most one candidate per lane ----
-    bool have = false;
+    bool have = false, examined = false, it_taken = false;
     uint32_t X = 0, Wv = 0;
     if (it < nit) {
       const Item I = items[it];
@@ -543,13 +549,16 @@ __global__ void __launch_bounds__(LV_THREADS) k_level(const Dev* __restrict__ dp
           X = I.x;
           Wv = (I.base + lane) * 64 + b;
         }
+        examined = have;
         if (!__ballot(wd != 0)) {
           inword = false;
           it += stride;
+          it_taken = true;
         }
       } else {
         const uint32_t extra = meta_extra(I.meta);
         const uint32_t v = meta_vstart(I.meta) + lane;
+        examined = lane < len;
         if (lane < len) {
           if (extra && v == 0) {
             have = true;
@@ -567,6 +576,7 @@ __global__ void __launch_bounds__(LV_THREADS) k_level(const Dev* __restrict__ dp
           }
         }
         it += stride;
+        it_taken = true;
       }
     }
     // quick filters: a real pair, still in the j-ball, not within j-1 hops
@@ -584,6 +594,11 @@ __global__ void __launch_bounds__(LV_THREADS) k_level(const Dev* __restrict__ dp
       }
     }
     const uint64_t bal = __ballot(have);
+    if (counting && lane == 0) {
+      if (it_taken) atomicAdd(&s_stat[0], 1u);
+      atomicAdd(&s_stat[1], (uint32_t)__popcll(__ballot(examined)));
+      atomicAdd(&s_stat[2], (uint32_t)__popcll(bal));
+    }
     uint32_t slot = 0;
     if (lane == 0 && bal) slot = atomicAdd(&s_count, (uint32_t)__popcll(bal));
     slot = __shfl(slot, 0, WAVE) + (uint32_t)__popcll(bal & ((1ull << lane) - 1));
@@ -606,6 +621,7 @@ __global__ void __launch_bounds__(LV_THREADS) k_level(const Dev* __restrict__ dp
     if (n + LV_THREADS <= LV_CAP && busy) continue;
     // ---- flush: probe every buffered pair ----
     const uint32_t total = block_scan_cap(cdeg, coff, n, s_wsum);
+    if (counting && threadIdx.x == 0) s_stat[3] += total;
     for (uint32_t pidx = threadIdx.x; pidx < total; pidx += LV_THREADS) {
       uint32_t lo = 0, hi = n;
       while (hi - lo > 1) {
@@ -632,6 +648,7 @@ __global__ void __launch_bounds__(LV_THREADS) k_level(const Dev* __restrict__ dp
         if (w1) atomicOr(&row(d.Dm[j], d.W, x)[w >> 6], bx);
         if (w2) atomicOr(&row(d.Dm[j], d.W, w)[x >> 6], bw);
       }
+      if (counting && (w1 || w2)) atomicAdd(&s_stat[4], (uint32_t)w1 + (uint32_t)w2);
       const uint64_t exw = ((uint64_t)x << 32) | w, ewx = ((uint64_t)w << 32) | x;
       record_events(d, j, rc.p, (uint32_t)w1 + (uint32_t)w2, w1 ? exw : ewx, ewx);
       if (j == d.h) {
@@ -647,6 +664,10 @@ __global__ void __launch_bounds__(LV_THREADS) k_level(const Dev* __restrict__ dp
     if (threadIdx.x == 0) s_count = 0;
     __syncthreads();
     if (!busy) break;
+  }
+  if (counting) {
+    __syncthreads();
+    if (threadIdx.x < 5) d.spart[threadIdx.x * STAT_GRID + blockIdx.x] = s_stat[threadIdx.x];
   }
 }
 
@@ -670,13 +691,19 @@ __global__ void __launch_bounds__(256) k_support(const Dev* __restrict__ dp) {
   const RoundCtx rc = round_ctx(c);
   const uint32_t nit = min(c->nit[list], d.itcap);
   const uint32_t lane = lane_id(), wpb = blockDim.x / WAVE;
+  __shared__ uint32_t s_stat[3];  // stats mode: items, slots, hits
+  const bool counting = d.spart != nullptr;
+  if (counting) {
+    if (threadIdx.x < 3) s_stat[threadIdx.x] = 0;
+    __syncthreads();
+  }
   const uint64_t* Lh = d.L[d.h];
   const uint64_t* Dh = d.Dm[d.h];
   uint32_t* Rn = d.R[rc.p ^ 1];
   for (uint32_t it = blockIdx.x * wpb + threadIdx.x / WAVE; it < nit; it += gridDim.x * wpb) {
     const Item I = d.itl[list][it];
     const uint32_t len = meta_len(I.meta);
-    bool push = false;
+    bool push = false, hit = false;
     uint32_t e = 0;
     if (lane < len) {
       const uint32_t q = I.base + lane;
@@ -686,12 +713,45 @@ __global__ void __launch_bounds__(256) k_support(const Dev* __restrict__ dp) {
         const size_t o = (size_t)I.y * d.W + (b >> 6);
         uint64_t word = Lh[o];
         if (I.x < b) word |= Dh[o];
-        if ((word >> (b & 63)) & 1ull) push = atomicSub(&d.sup[e], 1u) == rc.k - 1;
+        hit = (word >> (b & 63)) & 1ull;
+        if (hit) push = atomicSub(&d.sup[e], 1u) == rc.k - 1;
       }
     }
     const uint32_t slot = wave_reserve(&c->nPush, push ? 1u : 0u);
     if (push) Rn[slot] = e;
+    if (counting) {
+      const uint32_t hits = (uint32_t)__popcll(__ballot(hit));
+      if (lane == 0) {
+        atomicAdd(&s_stat[0], 1u);
+        atomicAdd(&s_stat[1], len);
+        atomicAdd(&s_stat[2], hits);
+      }
+    }
   }
+  if (counting) {
+    __syncthreads();
+    if (threadIdx.x < 3) d.spart[(5 + threadIdx.x) * STAT_GRID + blockIdx.x] = s_stat[threadIdx.x];
+  }
+}
+
+// Stats mode: fold the per-workgroup counters of one launch into Ctl::stat.
+__global__ void k_stats_fold(const Dev* __restrict__ dp, uint32_t first, uint32_t count,
+                             uint32_t grid) {
+  const Dev& d = *dp;
+  __shared__ uint64_t acc[NSTAT];
+  if (threadIdx.x < NSTAT) acc[threadIdx.x] = 0;
+  __syncthreads();
+  for (uint32_t c = first; c < first + count; ++c) {
+    uint64_t s = 0;
+    for (uint32_t b = threadIdx.x; b < grid; b += blockDim.x) {
+      s += d.spart[c * STAT_GRID + b];
+      d.spart[c * STAT_GRID + b] = 0;  // a launch that returns early leaves zeros
+    }
+    atomicAdd((unsigned long long*)&acc[c], (unsigned long long)s);
+  }
+  __syncthreads();
+  if (threadIdx.x < NSTAT && threadIdx.x >= first && threadIdx.x < first + count)
+    d.ctl->stat[threadIdx.x] += acc[threadIdx.x];
 }
 
 // ---- K5: end of round ------------------------------------------------------
