@@ -69,7 +69,7 @@ def roofline_from_stats(st: dict, workload: str):
     per_launch = alg_bytes / launches
     achieved = per_launch / (avg_ms * 1e-3) / 1e9 if avg_ms > 0 else 0.0
     traffic = None
-    tfile = PROFILES / f"traffic_{KERNEL_SYMBOL[dom]}_{workload}.json"
+    tfile = PROFILES / f"traffic_{KERNEL_SYMBOL[dom]}_{workload}.txt"
     if tfile.exists():
         t = json.loads(tfile.read_text())
         if t.get("source_sha") == kernel_source_sha():

@@ -1,0 +1,97 @@
+"""Summarise rocprofv3 databases of a bench run into short text files.
+
+    python -m paper_2411_06405_amd.profsum TRACE_DB FETCH_DB WRITE_DB OUTDIR TAG CMD
+
+Writes OUTDIR/kernels_TAG.txt (per-kernel dispatch count and durations from
+--kernel-trace), OUTDIR/hbm_counters_TAG.txt (mean FETCH_SIZE / WRITE_SIZE per
+dispatch, KiB) and OUTDIR/traffic_k_level_TAG.txt / traffic_k_support_TAG.txt
+(HBM bytes per launch of the round kernels, scaled by what the same counters
+read for a 256 MiB device-to-device copy).
+"""
+from __future__ import annotations
+
+import hashlib
+import json
+import sqlite3
+import sys
+from pathlib import Path
+
+import numpy as np
+
+COPY_BYTES = 256 << 20
+
+
+def short(name: str) -> str:
+    return name.split("(")[0].replace("hotruss::", "")
+
+
+def kernel_table(db: str):
+    c = sqlite3.connect(db)
+    rows = {}
+    for name, dur in c.execute("select name, end - start from kernels"):
+        rows.setdefault(name, []).append(dur / 1e3)
+    out = []
+    for name, d in sorted(rows.items(), key=lambda kv: -sum(kv[1])):
+        d = np.array(d)
+        out.append((short(name), len(d), d.sum() / 1e3, d.mean(), np.percentile(d, 50),
+                    np.percentile(d, 90), d.max()))
+    return out
+
+
+def counter_table(db: str, counter: str):
+    c = sqlite3.connect(db)
+    rows = {}
+    q = "select kernel_name, value from counters_collection where counter_name = ?"
+    for name, val in c.execute(q, (counter,)):
+        rows.setdefault(name, []).append(float(val))
+    return {name: np.array(v) for name, v in rows.items()}
+
+
+def main(trace_db, fetch_db, write_db, outdir, tag, cmd):
+    outdir = Path(outdir)
+    outdir.mkdir(parents=True, exist_ok=True)
+    kt = kernel_table(trace_db)
+    lines = [f"# rocprofv3 --kernel-trace --stats -- {cmd}",
+             "# kernel, dispatches, total_ms, mean_us, p50_us, p90_us, max_us"]
+    for r in kt:
+        lines.append(f"{r[0]:40s} {r[1]:8d} {r[2]:10.3f} {r[3]:10.2f} {r[4]:10.2f} {r[5]:10.2f} {r[6]:10.1f}")
+    (outdir / f"kernels_{tag}.txt").write_text("\n".join(lines) + "\n")
+    fetch = counter_table(fetch_db, "FETCH_SIZE")
+    write = counter_table(write_db, "WRITE_SIZE")
+    # calibration: the large device-to-device copy dispatches
+    def copy_kib(tab):
+        vals = [v for name, arr in tab.items() if "copy" in name.lower() for v in arr
+                if v > COPY_BYTES / 1024 * 0.5]
+        return float(np.median(vals)) if vals else None
+    cf, cw = copy_kib(fetch), copy_kib(write)
+    sf = (COPY_BYTES / 1024) / cf if cf else None
+    sw = (COPY_BYTES / 1024) / cw if cw else None
+    lines = [f"# rocprofv3 --pmc FETCH_SIZE -- {cmd}", f"# rocprofv3 --pmc WRITE_SIZE -- {cmd}",
+             f"# calibration: 256 MiB device copy reads FETCH_SIZE {cf} KiB (scale {sf}), "
+             f"WRITE_SIZE {cw} KiB (scale {sw})",
+             "# kernel, dispatches, mean FETCH_SIZE KiB, mean WRITE_SIZE KiB"]
+    names = sorted(set(fetch) | set(write), key=lambda n: -float(fetch.get(n, np.zeros(1)).sum()))
+    for n in names:
+        f = fetch.get(n, np.zeros(0))
+        w = write.get(n, np.zeros(0))
+        lines.append(f"{short(n):40s} {len(f):8d} {f.mean() if len(f) else 0:14.2f} "
+                     f"{w.mean() if len(w) else 0:14.2f}")
+    (outdir / f"hbm_counters_{tag}.txt").write_text("\n".join(lines) + "\n")
+    src = Path(__file__).resolve().parent / "csrc" / "hotruss_kernels.hip"
+    sha = hashlib.sha256(src.read_bytes()).hexdigest()[:16]
+    for kname in ("k_level", "k_support"):
+        full = [n for n in fetch if short(n) == kname]
+        if not full or sf is None or sw is None:
+            continue
+        f = fetch[full[0]]
+        w = write.get(full[0], np.zeros_like(f))
+        per_launch = float(f.mean() * 1024 * sf + w.mean() * 1024 * sw)
+        (outdir / f"traffic_{kname}_{tag}.txt").write_text(json.dumps({
+            "kernel": kname, "source_sha": sha, "launches": int(len(f)),
+            "fetch_kib_per_launch": float(f.mean()), "write_kib_per_launch": float(w.mean()),
+            "fetch_scale": sf, "write_scale": sw, "bytes_per_launch": per_launch,
+            "command": cmd}, indent=1) + "\n")
+
+
+if __name__ == "__main__":
+    main(*sys.argv[1:7])
