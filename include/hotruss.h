@@ -129,12 +129,27 @@ hoStatus hoTrussDecompose(const uint32_t *row_ptr, const uint32_t *col_idx,
 /* Counters of the last hoTrussDecompose on this host thread (host pointer). */
 hoStatus hoTrussLastStats(hoStats *out);
 
-/* Many independent graphs in one call.  row_ptr_cat holds graph g's local
- * (n_g+1)-entry row_ptr at offset vtx_off[g] + g; col_idx_cat holds its local
- * ids at offset adj_off[g]; its outputs start at edge_off[g].  vtx_off,
- * adj_off and edge_off are HOST arrays of B+1 entries (prefix sums of n_g,
- * 2m_g and m_g); h is a HOST array of B hop thresholds.  Results equal B
- * separate hoTrussDecompose calls (components never interact). */
+/* Many independent graphs in one call (batched decomposition: the same
+ * per-graph computation as hoTrussDecompose, graphs sharing the GPU).
+ * row_ptr_cat holds graph g's local (n_g+1)-entry row_ptr at offset
+ * vtx_off[g] + g; col_idx_cat holds its local ids at offset adj_off[g]; its
+ * outputs start at edge_off[g] of out_trussness_cat / out_round_cat (the
+ * latter may be NULL).  vtx_off, adj_off and edge_off are HOST arrays of B+1
+ * entries (prefix sums of n_g, 2m_g and m_g); h is a HOST array of B hop
+ * thresholds (each 1..16 after clamping at n_g - 1).  Results are identical to
+ * B separate hoTrussDecompose calls (components never interact).
+ *
+ * Execution: graphs are admitted largest workspace first into up to 256
+ * concurrent slots carved from the workspace; one replay of a captured step
+ * graph advances every active slot by one of its own peel rounds, and finished
+ * slots are refilled between replays.  Any workspace at least as large as the
+ * largest single graph's share works; more lets more graphs run together.
+ * hoTrussBatchedWorkspaceBytes returns the size that lets the 64 largest
+ * graphs run at once (or all of them, if smaller); 0 on invalid arguments.
+ * A graph that cannot fit the workspace at all returns HO_ERR_WORKSPACE; a
+ * malformed CSR in any graph returns HO_ERR_BAD_CSR (the other graphs'
+ * outputs are still written).  tune->grid_blocks, if set, is the total
+ * workgroup count shared by the slots. */
 size_t hoTrussBatchedWorkspaceBytes(const uint64_t *vtx_off, const uint64_t *edge_off,
                                     const uint32_t *h, uint32_t B, const hoTuning *tune);
 hoStatus hoTrussDecomposeBatched(const uint32_t *row_ptr_cat, const uint32_t *col_idx_cat,
@@ -143,6 +158,48 @@ hoStatus hoTrussDecomposeBatched(const uint32_t *row_ptr_cat, const uint32_t *co
                                  uint32_t *out_trussness_cat, uint32_t *out_round_cat,
                                  void *workspace, size_t workspace_bytes,
                                  const hoTuning *tune, hipStream_t stream);
+
+/* Sessions: continuous batching of decomposition requests that arrive over
+ * time (a serving loop).  A session owns a caller-provided device memory pool
+ * and up to max_slots concurrent decompositions, all on one stream.
+ *
+ *   hoSessionCreate   pool (device, pool_bytes) and stream are borrowed until
+ *                     hoSessionDestroy; max_h (1..16) bounds the requests' h.
+ *                     Writes the session handle to *out (host).
+ *   hoSubmit          queues one graph (same CSR conventions and outputs as
+ *                     hoTrussDecompose); CSR and output buffers must stay valid
+ *                     until the ticket is done.  Host-only: no device work.
+ *                     HO_ERR_BUDGET if the graph's share can never fit the
+ *                     pool; HO_ERR_INVALID_ARG if h exceeds max_h.  Writes a
+ *                     ticket (host).  An empty graph (m == 0) is done at once.
+ *   hoSessionProgress admits queued requests first-come first-served while a
+ *                     slot and pool memory are free (a request too large for
+ *                     the memory free now waits, and later smaller ones may
+ *                     pass it), then replays the step graph up to
+ *                     max_graph_launches times (0: until nothing is queued or
+ *                     running), retiring finished requests.  Blocks on
+ *                     `stream`.  Reports active and queued counts (host, may
+ *                     be NULL).
+ *   hoPoll            *done (host) = 1 once the ticket's outputs are final;
+ *                     returns that request's status (HO_ERR_BAD_CSR for a
+ *                     malformed graph, HO_ERR_CANCELLED if cancelled).
+ *   hoCancel          removes a request that is still queued; HO_ERR_BUSY if
+ *                     it already started or finished.
+ *   hoSessionDestroy  waits for the stream and frees the host-side state; the
+ *                     pool is the caller's to free.
+ * Calls on one session may come from several host threads: each takes the
+ * session's lock, so they serialize. */
+typedef struct hoSession hoSession;
+hoStatus hoSessionCreate(void *pool, size_t pool_bytes, uint32_t max_slots, uint32_t max_h,
+                         hipStream_t stream, hoSession **out);
+hoStatus hoSubmit(hoSession *s, const uint32_t *row_ptr, const uint32_t *col_idx, uint32_t n,
+                  uint64_t m, uint32_t h, uint32_t *out_trussness, uint32_t *out_round,
+                  uint64_t *out_ticket);
+hoStatus hoSessionProgress(hoSession *s, uint32_t max_graph_launches, uint32_t *active,
+                           uint32_t *queued);
+hoStatus hoPoll(hoSession *s, uint64_t ticket, int *done);
+hoStatus hoCancel(hoSession *s, uint64_t ticket);
+hoStatus hoSessionDestroy(hoSession *s);
 
 const char *hoStatusString(hoStatus s);
 

@@ -3,9 +3,10 @@
 The computation lives in libhotruss.so (hand-written HIP kernels for gfx950,
 C ABI declared in include/hotruss.h); this package is its thin Python binding.
 """
-from ._lib import (HotrussError, Tuning, alloc_workspace, decompose, decompose_graph,
-                   h_support, h_support_graph, last_stats, lib, to_numpy_u32, workspace_bytes)
+from ._lib import (HotrussError, Session, Tuning, alloc_workspace, batched_workspace_bytes,
+                   decompose, decompose_batch, decompose_batched, decompose_graph, h_support,
+                   h_support_graph, last_stats, lib, to_numpy_u32, workspace_bytes)
 
-__all__ = ["HotrussError", "Tuning", "alloc_workspace", "decompose", "decompose_graph",
-           "h_support", "h_support_graph", "last_stats", "lib", "to_numpy_u32",
-           "workspace_bytes"]
+__all__ = ["HotrussError", "Session", "Tuning", "alloc_workspace", "batched_workspace_bytes",
+           "decompose", "decompose_batch", "decompose_batched", "decompose_graph", "h_support",
+           "h_support_graph", "last_stats", "lib", "to_numpy_u32", "workspace_bytes"]

@@ -63,12 +63,22 @@ def _declare(lib):
     lib.hoTrussLastStats.restype = C.c_int
     lib.hoStatusString.argtypes = [C.c_int]
     lib.hoStatusString.restype = C.c_char_p
-    if hasattr(lib, "hoTrussBatchedWorkspaceBytes"):
-        lib.hoTrussBatchedWorkspaceBytes.argtypes = [vp, vp, vp, u32, tp]
-        lib.hoTrussBatchedWorkspaceBytes.restype = sz
-        lib.hoTrussDecomposeBatched.argtypes = [vp, vp, vp, vp, vp, vp, u32, vp, vp, vp, sz,
-                                                tp, vp]
-        lib.hoTrussDecomposeBatched.restype = C.c_int
+    lib.hoTrussBatchedWorkspaceBytes.argtypes = [vp, vp, vp, u32, tp]
+    lib.hoTrussBatchedWorkspaceBytes.restype = sz
+    lib.hoTrussDecomposeBatched.argtypes = [vp, vp, vp, vp, vp, vp, u32, vp, vp, vp, sz, tp, vp]
+    lib.hoTrussDecomposeBatched.restype = C.c_int
+    lib.hoSessionCreate.argtypes = [vp, sz, u32, u32, vp, C.POINTER(vp)]
+    lib.hoSessionCreate.restype = C.c_int
+    lib.hoSubmit.argtypes = [vp, vp, vp, u32, u64, u32, vp, vp, C.POINTER(u64)]
+    lib.hoSubmit.restype = C.c_int
+    lib.hoSessionProgress.argtypes = [vp, u32, C.POINTER(u32), C.POINTER(u32)]
+    lib.hoSessionProgress.restype = C.c_int
+    lib.hoPoll.argtypes = [vp, u64, C.POINTER(C.c_int)]
+    lib.hoPoll.restype = C.c_int
+    lib.hoCancel.argtypes = [vp, u64]
+    lib.hoCancel.restype = C.c_int
+    lib.hoSessionDestroy.argtypes = [vp]
+    lib.hoSessionDestroy.restype = C.c_int
     return lib
 
 
@@ -82,7 +92,9 @@ def load():
 lib = load()
 
 EXPORTS = ["hoStatusString", "hoTrussWorkspaceBytes", "hoTrussHSupport", "hoTrussDecompose",
-           "hoTrussLastStats", "hoTrussBatchedWorkspaceBytes", "hoTrussDecomposeBatched"]
+           "hoTrussLastStats", "hoTrussBatchedWorkspaceBytes", "hoTrussDecomposeBatched",
+           "hoSessionCreate", "hoSubmit", "hoSessionProgress", "hoPoll", "hoCancel",
+           "hoSessionDestroy"]
 
 
 def _check(rc: int, what: str):
@@ -176,3 +188,122 @@ def decompose_graph(g, h: int, **kw):
 
 def h_support_graph(g, h: int, **kw) -> np.ndarray:
     return to_numpy_u32(h_support(g.row_ptr, g.col_idx, g.n, h, **kw))
+
+
+def _host_ptr(a: np.ndarray, dtype) -> tuple:
+    arr = np.ascontiguousarray(a, dtype=dtype)
+    return arr, arr.ctypes.data
+
+
+def batched_workspace_bytes(vtx_off, edge_off, h, tune=None) -> int:
+    vo, vop = _host_ptr(vtx_off, np.uint64)
+    eo, eop = _host_ptr(edge_off, np.uint64)
+    hh, hp = _host_ptr(h, np.uint32)
+    return int(lib.hoTrussBatchedWorkspaceBytes(vop, eop, hp, hh.size, _tuning(tune)))
+
+
+def decompose_batched(row_ptr_cat, col_idx_cat, vtx_off, adj_off, edge_off, h,
+                      with_rounds: bool = True, workspace=None, tune=None, stream=None,
+                      device="cuda"):
+    """Batched decomposition of concatenated graphs (offset arrays on the host).
+
+    Returns (t_cat, rho_cat) device int32 tensors in concatenated edge order."""
+    rp = _dev_u32(row_ptr_cat, device)
+    ci = _dev_u32(col_idx_cat, device)
+    vo, vop = _host_ptr(vtx_off, np.uint64)
+    ao, aop = _host_ptr(adj_off, np.uint64)
+    eo, eop = _host_ptr(edge_off, np.uint64)
+    hh, hp = _host_ptr(h, np.uint32)
+    B = hh.size
+    mt = int(eo[-1]) if B else 0
+    t = torch.empty(max(mt, 1), dtype=torch.int32, device=device)
+    rho = torch.empty(max(mt, 1), dtype=torch.int32, device=device) if with_rounds else None
+    if workspace is None:
+        nb = batched_workspace_bytes(vo, eo, hh, tune)
+        workspace = torch.empty(max(nb, 1), dtype=torch.uint8, device=device)
+    rc = lib.hoTrussDecomposeBatched(rp.data_ptr(), ci.data_ptr(), vop, aop, eop, hp, B,
+                                     t.data_ptr(), rho.data_ptr() if rho is not None else None,
+                                     workspace.data_ptr(), workspace.numel(), _tuning(tune),
+                                     _stream(stream))
+    _check(rc, "hoTrussDecomposeBatched")
+    return t[:mt], (rho[:mt] if rho is not None else None)
+
+
+def decompose_batch(batch, **kw):
+    """Convenience for graphgen.Batch: returns per-graph numpy (t, rho) lists."""
+    t, rho = decompose_batched(batch.row_ptr_cat, batch.col_idx_cat, batch.vtx_off,
+                               batch.adj_off, batch.edge_off, batch.h, **kw)
+    tn = to_numpy_u32(t)
+    rn = to_numpy_u32(rho) if rho is not None else None
+    eo = batch.edge_off.astype(np.int64)
+    ts = [tn[eo[g]:eo[g + 1]] for g in range(batch.B)]
+    rs = [rn[eo[g]:eo[g + 1]] for g in range(batch.B)] if rn is not None else None
+    return ts, rs
+
+
+class Session:
+    """Continuous-batching session over a device memory pool (hoSession*).
+
+    submit() queues a graph whose device CSR and outputs the session keeps
+    alive until the request is done; progress() admits and runs rounds."""
+
+    def __init__(self, pool_bytes: int, max_slots: int = 64, max_h: int = 4, stream=None,
+                 device="cuda"):
+        self.device = device
+        self.pool = torch.empty(pool_bytes, dtype=torch.uint8, device=device)
+        self.stream = stream
+        self._h = C.c_void_p()
+        rc = lib.hoSessionCreate(self.pool.data_ptr(), pool_bytes, max_slots, max_h,
+                                 _stream(stream), C.byref(self._h))
+        _check(rc, "hoSessionCreate")
+        self._keep = {}
+
+    def submit(self, row_ptr, col_idx, n: int, h: int) -> int:
+        rp = _dev_u32(row_ptr, self.device)
+        ci = _dev_u32(col_idx, self.device)
+        m = ci.numel() // 2
+        t = torch.empty(max(m, 1), dtype=torch.int32, device=self.device)
+        rho = torch.empty(max(m, 1), dtype=torch.int32, device=self.device)
+        ticket = C.c_uint64()
+        rc = lib.hoSubmit(self._h, rp.data_ptr(), ci.data_ptr(), n, m, h, t.data_ptr(),
+                          rho.data_ptr(), C.byref(ticket))
+        _check(rc, "hoSubmit")
+        self._keep[ticket.value] = (rp, ci, t, rho, m)
+        return ticket.value
+
+    def progress(self, max_graph_launches: int = 0):
+        a, q = C.c_uint32(), C.c_uint32()
+        rc = lib.hoSessionProgress(self._h, max_graph_launches, C.byref(a), C.byref(q))
+        _check(rc, "hoSessionProgress")
+        return a.value, q.value
+
+    def poll(self, ticket: int) -> bool:
+        done = C.c_int()
+        rc = lib.hoPoll(self._h, ticket, C.byref(done))
+        _check(rc, "hoPoll")
+        return bool(done.value)
+
+    def status(self, ticket: int) -> int:
+        done = C.c_int()
+        return int(lib.hoPoll(self._h, ticket, C.byref(done)))
+
+    def cancel(self, ticket: int) -> None:
+        _check(lib.hoCancel(self._h, ticket), "hoCancel")
+
+    def result(self, ticket: int):
+        """(t, rho) numpy uint32 arrays of a finished request; releases its buffers."""
+        if not self.poll(ticket):
+            raise HotrussError(-7, "request not finished")
+        rp, ci, t, rho, m = self._keep.pop(ticket)
+        return to_numpy_u32(t[:m]), to_numpy_u32(rho[:m])
+
+    def close(self):
+        if self._h:
+            _check(lib.hoSessionDestroy(self._h), "hoSessionDestroy")
+            self._h = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

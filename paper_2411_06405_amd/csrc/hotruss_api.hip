@@ -5,6 +5,9 @@
 #include <cstring>
 #include <mutex>
 #include <vector>
+#include <map>
+#include <new>
+#include <functional>
 
 #include "../../include/hotruss.h"
 #include "hotruss_dev.h"
@@ -29,7 +32,7 @@ struct Plan {
   uint64_t m = 0;
   bool full = true;  // decomposition (false: support only)
   size_t off_ctl, off_eid, off_eu, off_ev, off_s1, off_s2, off_srem, off_upcnt, off_upoff,
-      off_scan, off_minpart, off_dev, off_spart, off_sup, off_rho, off_R0, off_R1, off_L[HMAX + 1],
+      off_scan, off_minpart, off_sup, off_rho, off_R0, off_R1, off_L[HMAX + 1],
       off_Dm[HMAX + 1], off_evl[HMAX + 1][2], off_itl[HMAX + 2];
   size_t total = 0;
 };
@@ -43,7 +46,8 @@ uint32_t clamp_cap(uint64_t want, uint64_t lo, uint64_t hi) {
   return (uint32_t)std::min<uint64_t>(std::max<uint64_t>(want, lo), hi);
 }
 
-bool make_plan(uint32_t n, uint64_t m, uint32_t h, const hoTuning* tune, bool full, Plan* P) {
+bool make_plan(uint32_t n, uint64_t m, uint32_t h, const hoTuning* tune, bool full, Plan* P,
+               uint64_t cap_factor = 128) {
   if (h == 0 || m >= (1ull << 31) || n == 0xffffffffu) return false;
   if (n > 1 && h > n - 1) h = n - 1;  // any h beyond n-1 is the same as n-1
   if (h == 0) h = 1;
@@ -54,9 +58,9 @@ bool make_plan(uint32_t n, uint64_t m, uint32_t h, const hoTuning* tune, bool fu
   // Lists are sized so that a round rarely overflows them (a round that does
   // runs its level or support step through the serial kernels, far slower).
   p.evcap = tune && tune->event_capacity ? tune->event_capacity
-                                         : clamp_cap(128 * m, 1u << 20, 1u << 27);
+                                         : clamp_cap(cap_factor * m, 1u << 16, 1u << 27);
   p.itcap = tune && tune->item_capacity ? tune->item_capacity
-                                        : clamp_cap(128 * m, 1u << 20, 1u << 27);
+                                        : clamp_cap(cap_factor * m, 1u << 16, 1u << 27);
   const size_t rowbytes = (size_t)p.W * 8;
   if (rowbytes > MAX_LDS_ROW) return false;  // rows are built in LDS
   size_t o = 0;
@@ -72,8 +76,6 @@ bool make_plan(uint32_t n, uint64_t m, uint32_t h, const hoTuning* tune, bool fu
   p.off_upoff = take(4 * (size_t)n + 4);
   p.off_scan = take(4 * ((size_t)n / 1024 + 2));
   p.off_minpart = take(4 * MIN_PART);
-  p.off_dev = take(sizeof(Dev));
-  p.off_spart = take(4ull * NSTAT * STAT_GRID);
   p.off_sup = take(4 * m + 4);
   p.off_rho = take(full ? 4 * m + 4 : 0);
   p.off_R0 = take(full ? 4 * m + 4 : 0);
@@ -121,8 +123,6 @@ unsigned grid_for(size_t items, unsigned per_block, unsigned cap_mult = 16) {
   return (unsigned)g;
 }
 
-thread_local uint32_t* stats_part_base = nullptr;  // workspace slot of the stats counters
-
 Dev carve(const Plan& p, void* ws, const uint32_t* rp, const uint32_t* ci, uint32_t* t,
           uint32_t* rho) {
   uintptr_t base = ((uintptr_t)ws + ALIGN - 1) / ALIGN * ALIGN;
@@ -134,7 +134,7 @@ Dev carve(const Plan& p, void* ws, const uint32_t* rp, const uint32_t* ci, uint3
   d.nnz = (uint32_t)(2 * p.m);
   d.evcap = p.evcap;
   d.itcap = p.itcap;
-  d.nminpart = std::min<uint32_t>(MIN_PART, grid_for(p.m, 256, 4));
+  d.nminpart = 1;  // set by the engine to its k_jump_min grid width
   d.ctl = (Ctl*)at(p.off_ctl);
   d.eid = (uint32_t*)at(p.off_eid);
   d.eu = (uint32_t*)at(p.off_eu);
@@ -146,10 +146,10 @@ Dev carve(const Plan& p, void* ws, const uint32_t* rp, const uint32_t* ci, uint3
   d.up_off = (uint32_t*)at(p.off_upoff);
   d.scan_tmp = (uint32_t*)at(p.off_scan);
   d.minpart = (uint32_t*)at(p.off_minpart);
-  d.self = (Dev*)at(p.off_dev);
+  d.self = nullptr;   // the engine's device-resident copy
   d.serial = 0;
   d.spart = nullptr;  // set in stats mode
-  stats_part_base = (uint32_t*)at(p.off_spart);
+  d.status = nullptr;
   d.sup = (uint32_t*)at(p.off_sup);
   d.t = t;
   d.rho = rho ? rho : (p.full ? (uint32_t*)at(p.off_rho) : nullptr);
@@ -215,73 +215,41 @@ hoStatus run_init(const Dev& d, uint32_t* out_sup, const hoTuning* tune, hipStre
   return HO_OK;
 }
 
-// Launch geometry of the round kernels.
+// Launch geometry of the round kernels (x: workgroups per slot).
 struct RoundGrid {
   unsigned jump, mark, level, support;
 };
 
-RoundGrid round_grid(const Dev& d, const hoTuning* tune) {
+RoundGrid plain_grid(uint64_t m, const hoTuning* tune) {
   RoundGrid g;
   const unsigned wide = tune && tune->grid_blocks ? tune->grid_blocks : (unsigned)num_cu() * 8;
-  g.jump = d.nminpart;
-  g.mark = std::max(1u, std::min(wide, grid_for(d.m, 256)));
-  g.level = wide;
-  g.support = wide;
+  g.jump = std::min<unsigned>(MIN_PART, grid_for(m, 256, 4));
+  g.mark = std::max(1u, std::min(wide, grid_for(m, 256)));
+  g.level = std::min<unsigned>(wide, STAT_GRID);
+  g.support = std::min<unsigned>(wide, STAT_GRID);
+  return g;
+}
+
+RoundGrid batch_grid(uint32_t slots, const hoTuning* tune) {
+  // about 8 workgroups per CU across all slots, at least 4 per slot
+  const unsigned total = tune && tune->grid_blocks ? tune->grid_blocks : (unsigned)num_cu() * 8;
+  const unsigned per = std::max(4u, std::min(256u, total / std::max(1u, slots)));
+  RoundGrid g{std::min<unsigned>(MIN_PART, per), per, per, per};
   return g;
 }
 
 // Kernel kinds timed in stats mode.
 enum { KT_SUPINIT = 0, KT_JUMP, KT_MARK, KT_LEVEL, KT_SUPPORT, KT_ADVANCE, KT_N };
 
-void launch_round(const Dev& d, const RoundGrid& g, hipStream_t s) {
+void launch_step(const Dev* devs, uint32_t S, uint32_t hmax, const RoundGrid& g, hipStream_t s) {
   const unsigned T = 256;
-  const Dev* dp = d.self;
-  hipLaunchKernelGGL(k_jump_min, dim3(g.jump), dim3(T), 0, s, dp);
-  hipLaunchKernelGGL(k_mark, dim3(g.mark), dim3(T), 0, s, dp);
-  for (uint32_t j = 2; j <= d.h; ++j)
-    hipLaunchKernelGGL(k_level, dim3(g.level), dim3(LV_THREADS), 0, s, dp, j);
-  hipLaunchKernelGGL(k_support, dim3(g.support), dim3(T), 0, s, dp);
-  hipLaunchKernelGGL(k_advance, dim3(1), dim3(64), 0, s, dp);
+  hipLaunchKernelGGL(k_jump_min, dim3(g.jump, S), dim3(T), 0, s, devs);
+  hipLaunchKernelGGL(k_mark, dim3(g.mark, S), dim3(T), 0, s, devs);
+  for (uint32_t j = 2; j <= hmax; ++j)
+    hipLaunchKernelGGL(k_level, dim3(g.level, S), dim3(LV_THREADS), 0, s, devs, j);
+  hipLaunchKernelGGL(k_support, dim3(g.support, S), dim3(T), 0, s, devs);
+  hipLaunchKernelGGL(k_advance, dim3(1, S), dim3(64), 0, s, devs);
 }
-
-// Captured round sequences, cached per device state (workspace, buffers).
-struct GraphEntry {
-  Dev key;
-  uint32_t rounds;
-  unsigned level_grid;
-  hipGraphExec_t exec;
-};
-std::mutex g_graph_mu;
-std::vector<GraphEntry> g_graphs;
-hipStream_t g_capture_stream = nullptr;
-
-hoStatus get_graph(const Dev& d, const RoundGrid& g, uint32_t rounds, hipGraphExec_t* out) {
-  std::lock_guard<std::mutex> lk(g_graph_mu);
-  for (auto& e : g_graphs)
-    if (e.rounds == rounds && e.key.self == d.self && e.key.h == d.h && e.key.m == d.m &&
-        e.key.nminpart == d.nminpart && e.level_grid == g.level) {
-      *out = e.exec;
-      return HO_OK;
-    }
-  if (!g_capture_stream) HIPCHK(hipStreamCreateWithFlags(&g_capture_stream, hipStreamNonBlocking));
-  hipGraph_t graph;
-  HIPCHK(hipStreamBeginCapture(g_capture_stream, hipStreamCaptureModeThreadLocal));
-  for (uint32_t i = 0; i < rounds; ++i) launch_round(d, g, g_capture_stream);
-  HIPCHK(hipStreamEndCapture(g_capture_stream, &graph));
-  hipGraphExec_t exec;
-  hipError_t err = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
-  (void)hipGraphDestroy(graph);
-  if (err != hipSuccess) return HO_ERR_HIP;
-  if (g_graphs.size() >= 64) {  // bounded cache: drop the oldest
-    (void)hipGraphExecDestroy(g_graphs.front().exec);
-    g_graphs.erase(g_graphs.begin());
-  }
-  g_graphs.push_back(GraphEntry{d, rounds, g.level, exec});
-  *out = exec;
-  return HO_OK;
-}
-
-uint32_t* g_done_host = nullptr;  // pinned {done, halt} words, one pair per graph in flight
 
 hoStatus read_ctl(const Dev& d, Ctl* host, hipStream_t s) {
   HIPCHK(hipMemcpyAsync(host, d.ctl, sizeof(Ctl), hipMemcpyDeviceToHost, s));
@@ -289,7 +257,7 @@ hoStatus read_ctl(const Dev& d, Ctl* host, hipStream_t s) {
   return HO_OK;
 }
 
-// Timing of the host-driven round steps (stats mode).
+// Timing of host-driven round steps (stats mode).
 struct StepTimer {
   bool on = false;
   hipEvent_t e0 = nullptr, e1 = nullptr;
@@ -311,11 +279,11 @@ struct StepTimer {
   }
 };
 
-// Run the round steps from `from` on (2..h: level j, h+1: support update,
-// h+2: end of round) from the host, taking the serial kernel for any step
-// whose chunked kernel halts on an overflowed work list.
-hoStatus steps_host(const Dev& d, const RoundGrid& g, hipStream_t s, uint32_t from, bool serial_first,
-                    StepTimer& tm) {
+// Run one slot's round steps from `from` on (2..h: level j, h+1: support
+// update) and end the round, from the host, taking the serial kernel for any
+// step whose chunked kernel halts on an overflowed work list.
+hoStatus steps_host(const Dev& d, const RoundGrid& g, hipStream_t s, uint32_t from,
+                    bool serial_first, StepTimer& tm) {
   const unsigned T = 256;
   const Dev* dp = d.self;
   Ctl c;
@@ -330,12 +298,12 @@ hoStatus steps_host(const Dev& d, const RoundGrid& g, hipStream_t s, uint32_t fr
         if (step <= d.h) hipLaunchKernelGGL(k_stats_fold, dim3(1), dim3(256), 0, s, dp, 0u, 5u, g.level);
         else hipLaunchKernelGGL(k_stats_fold, dim3(1), dim3(256), 0, s, dp, 5u, 3u, g.support);
       }
-      hoStatus st = read_ctl(d, &c, s);
-      if (st != HO_OK) return st;
+      HOCHK(read_ctl(d, &c, s));
       serial = c.halt != 0;
     }
     if (serial) {
       HIPCHK(hipMemsetAsync(&d.ctl->halt, 0, sizeof(uint32_t), s));
+      HIPCHK(hipMemsetAsync(&d.status[1], 0, sizeof(uint32_t), s));
       HOCHK(tm.begin(s));
       if (step <= d.h) hipLaunchKernelGGL(k_level_serial, dim3(g.level), dim3(T), 0, s, dp, step);
       else hipLaunchKernelGGL(k_support_serial, dim3(g.support), dim3(T), 0, s, dp);
@@ -349,72 +317,375 @@ hoStatus steps_host(const Dev& d, const RoundGrid& g, hipStream_t s, uint32_t fr
   return HO_OK;
 }
 
-// A graph stopped on a halted step: finish that round from the host.
-hoStatus finish_halted_round(const Dev& d, const RoundGrid& g, hipStream_t s, StepTimer& tm) {
-  Ctl c;
-  hoStatus st = read_ctl(d, &c, s);
-  if (st != HO_OK) return st;
-  if (!c.halt) return HO_OK;
-  return steps_host(d, g, s, c.halt_step, true, tm);
-}
+// ----------------------------------------------------------------- engine
+// A pool of device memory, S slots and a queue of decompositions.  Every
+// replay of the captured step graph advances each active slot by one of its
+// own peel rounds; finished slots are retired and queued graphs admitted
+// between graph launches (continuous batching).  The plain entry point is the
+// same engine with one slot and a full-GPU grid.
 
-// Peel rounds until the device reports completion: graphs of G rounds are
-// replayed with two in flight; the host only polls the {done, halt} words.
-hoStatus run_rounds_graph(const Dev& d, const hoTuning* tune, hipStream_t s) {
-  const RoundGrid g = round_grid(d, tune);
-  {
-    std::lock_guard<std::mutex> lk(g_graph_mu);
-    if (!g_done_host) HIPCHK(hipHostMalloc((void**)&g_done_host, 64, hipHostMallocDefault));
+struct Request {
+  const uint32_t* rp = nullptr;
+  const uint32_t* ci = nullptr;
+  uint32_t n = 0, h = 0;
+  uint64_t m = 0;
+  uint32_t* t = nullptr;
+  uint32_t* rho = nullptr;
+  hoTuning tune{};
+  bool has_tune = false;
+  int state = 0;  // 0 queued, 1 running, 2 finished, 3 cancelled
+  hoStatus result = HO_OK;
+  Plan plan;
+  int slot = -1;
+  size_t off = 0;
+};
+
+class Pool {  // first-fit allocator over [lo, hi), 256-byte granules
+ public:
+  void reset(size_t lo, size_t hi) {
+    free_.clear();
+    if (hi > lo) free_[lo] = hi - lo;
   }
-  hipEvent_t ev[2];
-  HIPCHK(hipEventCreateWithFlags(&ev[0], hipEventDisableTiming));
-  HIPCHK(hipEventCreateWithFlags(&ev[1], hipEventDisableTiming));
-  const uint32_t sizes[3] = {4, 32, 128};
-  hipGraphExec_t ex[3];
-  for (int i = 0; i < 3; ++i) {
-    hoStatus st = get_graph(d, g, sizes[i], &ex[i]);
-    if (st != HO_OK) return st;
+  bool alloc(size_t bytes, size_t* off) {
+    bytes = up(bytes);
+    for (auto it = free_.begin(); it != free_.end(); ++it)
+      if (it->second >= bytes) {
+        *off = it->first;
+        const size_t rest = it->second - bytes, at = it->first + bytes;
+        free_.erase(it);
+        if (rest) free_[at] = rest;
+        return true;
+      }
+    return false;
   }
-  volatile uint32_t* flag = g_done_host;
-  StepTimer tm;
-  uint64_t launched = 0, maxlaunch = 8 + 2 * (uint64_t)d.m;  // every round peels >= 1 edge
-  auto launch = [&](int slot) -> hoStatus {
-    const int which = launched == 0 ? 0 : launched == 1 ? 1 : 2;
-    HIPCHK(hipGraphLaunch(ex[which], s));
-    HIPCHK(hipMemcpyAsync((void*)&flag[2 * slot], &d.ctl->done, 8, hipMemcpyDeviceToHost, s));
-    HIPCHK(hipEventRecord(ev[slot], s));
-    ++launched;
-    return HO_OK;
-  };
-  hoStatus st = launch(0);
-  if (st == HO_OK) st = launch(1);
-  int cur = 0;
-  while (st == HO_OK) {
-    HIPCHK(hipEventSynchronize(ev[cur]));
-    if (flag[2 * cur]) break;  // done
-    if (launched > maxlaunch) { st = HO_ERR_INTERNAL; break; }
-    if (flag[2 * cur + 1]) {  // halted: drain, finish the round here, restart
-      HIPCHK(hipStreamSynchronize(s));
-      st = finish_halted_round(d, g, s, tm);
-      if (st != HO_OK) break;
-      st = launch(0);
-      if (st == HO_OK) st = launch(1);
-      cur = 0;
-      continue;
+  void release(size_t off, size_t bytes) {
+    bytes = up(bytes);
+    auto it = free_.emplace(off, bytes).first;
+    auto nx = std::next(it);
+    if (nx != free_.end() && it->first + it->second == nx->first) {
+      it->second += nx->second;
+      free_.erase(nx);
     }
-    st = launch(cur);
-    cur ^= 1;
+    if (it != free_.begin()) {
+      auto pv = std::prev(it);
+      if (pv->first + pv->second == it->first) {
+        pv->second += it->second;
+        free_.erase(it);
+      }
+    }
   }
-  HIPCHK(hipStreamSynchronize(s));
-  (void)hipEventDestroy(ev[0]);
-  (void)hipEventDestroy(ev[1]);
-  return st;
+  size_t largest() const {
+    size_t b = 0;
+    for (auto& kv : free_) b = std::max(b, kv.second);
+    return b;
+  }
+
+ private:
+  std::map<size_t, size_t> free_;
+};
+
+// Instantiated step graphs, kept for the life of the process: a graph's
+// kernel nodes hold the descriptor array's address and the grid, so the key
+// is those plus the device.  Beyond GRAPH_CACHE keys an engine owns its graphs.
+struct GraphKey {
+  int dev;
+  const void* devs;
+  uint32_t S, hmax, jump, mark, level, support;
+  bool operator==(const GraphKey& o) const {
+    return dev == o.dev && devs == o.devs && S == o.S && hmax == o.hmax && jump == o.jump &&
+           mark == o.mark && level == o.level && support == o.support;
+  }
+};
+struct GraphCacheEntry {
+  GraphKey key;
+  hipGraphExec_t exec[3];
+};
+constexpr size_t GRAPH_CACHE = 64;
+std::mutex g_graph_mu;
+std::vector<GraphCacheEntry> g_graph_cache;
+
+// Engine header: S slot descriptors, S {done, halt} status pairs, the stats
+// counters and the control block of an idle slot (finished, so every round
+// kernel returns at once).
+size_t engine_header_bytes(uint32_t S) {
+  return up(sizeof(Dev) * S) + up(8ull * S) + up(4ull * NSTAT * STAT_GRID) + up(sizeof(Ctl));
 }
 
-// Debug / stats form: every round driven from the host, optional timing.
-hoStatus run_rounds_host(const Dev& d, const hoTuning* tune, hipStream_t s, bool timed,
-                         double* kms, uint64_t* klaunch) {
-  const RoundGrid g = round_grid(d, tune);
+class Engine {
+ public:
+  hipStream_t s = nullptr;
+  uintptr_t base = 0;
+  size_t bytes = 0;
+  uint32_t S = 1, hmax = 1;
+  uint64_t cap_factor = 128;
+  RoundGrid g{};
+  bool plain = false;
+  Dev* devs_d = nullptr;
+  uint32_t* status_d = nullptr;
+  uint32_t* spart_d = nullptr;
+  std::vector<int> slot_req;
+  std::vector<Dev> slot_dev;
+  std::vector<uint64_t> slot_since;  // first graph launch that can report on the slot
+  Pool pool;
+  std::vector<Request> reqs;
+  std::vector<size_t> queue;
+  Ctl* idle_ctl_d = nullptr;
+  uint32_t* hstat = nullptr;  // pinned: 2 buffers x S x {done, halt}
+  Dev* idle_h = nullptr;      // pinned: descriptor of each idle slot
+  Dev* dev_h = nullptr;       // pinned: staging of each admitted slot's descriptor
+  hipEvent_t ev[2] = {nullptr, nullptr};
+  hipGraphExec_t exec[3] = {nullptr, nullptr, nullptr};
+  bool owns_graphs = false;
+  bool copy_failed = false;
+  uint64_t steps = 0;
+
+  ~Engine() {
+    if (s) (void)hipStreamSynchronize(s);  // nothing in flight may target freed host buffers
+    if (owns_graphs)
+      for (auto& e : exec)
+        if (e) (void)hipGraphExecDestroy(e);
+    for (auto& e : ev)
+      if (e) (void)hipEventDestroy(e);
+    if (hstat) (void)hipHostFree(hstat);
+    if (idle_h) (void)hipHostFree(idle_h);
+    if (dev_h) (void)hipHostFree(dev_h);
+  }
+
+  hoStatus init(void* ws, size_t ws_bytes, uint32_t slots, uint32_t hmax_, const RoundGrid& grid,
+                hipStream_t stream, bool plain_) {
+    s = stream;
+    base = ((uintptr_t)ws + ALIGN - 1) / ALIGN * ALIGN;
+    if (ws_bytes < ALIGN + engine_header_bytes(slots)) return HO_ERR_WORKSPACE;
+    bytes = ws_bytes - (base - (uintptr_t)ws);
+    S = slots;
+    hmax = hmax_;
+    g = grid;
+    plain = plain_;
+    devs_d = (Dev*)base;
+    status_d = (uint32_t*)(base + up(sizeof(Dev) * S));
+    spart_d = (uint32_t*)(base + up(sizeof(Dev) * S) + up(8ull * S));
+    idle_ctl_d = (Ctl*)(base + up(sizeof(Dev) * S) + up(8ull * S) + up(4ull * NSTAT * STAT_GRID));
+    pool.reset(engine_header_bytes(S), bytes);
+    slot_req.assign(S, -1);
+    slot_dev.assign(S, Dev{});
+    slot_since.assign(S, 0);
+    HIPCHK(hipHostMalloc((void**)&hstat, 16ull * S + sizeof(Ctl), hipHostMallocDefault));
+    HIPCHK(hipHostMalloc((void**)&idle_h, sizeof(Dev) * S, hipHostMallocDefault));
+    HIPCHK(hipHostMalloc((void**)&dev_h, sizeof(Dev) * S, hipHostMallocDefault));
+    HIPCHK(hipEventCreateWithFlags(&ev[0], hipEventDisableTiming));
+    HIPCHK(hipEventCreateWithFlags(&ev[1], hipEventDisableTiming));
+    // every slot starts idle: finished status, a descriptor with no levels
+    // whose control block says finished, so every round kernel returns at once
+    for (uint32_t i = 0; i < 2 * S; ++i) hstat[i] = (i % 2 == 0) ? 1u : 0u;
+    Ctl* hc = (Ctl*)(hstat + 4ull * S);
+    memset(hc, 0, sizeof(Ctl));
+    hc->done = 1;
+    for (uint32_t i = 0; i < S; ++i) {
+      memset(&idle_h[i], 0, sizeof(Dev));
+      idle_h[i].ctl = idle_ctl_d;
+      idle_h[i].status = status_d + 2 * i;
+      idle_h[i].self = devs_d + i;
+    }
+    HIPCHK(hipMemcpyAsync(idle_ctl_d, hc, sizeof(Ctl), hipMemcpyHostToDevice, s));
+    HIPCHK(hipMemcpyAsync(status_d, hstat, 8ull * S, hipMemcpyHostToDevice, s));
+    HIPCHK(hipMemcpyAsync(devs_d, idle_h, sizeof(Dev) * S, hipMemcpyHostToDevice, s));
+    HIPCHK(hipStreamSynchronize(s));
+    return HO_OK;
+  }
+
+  size_t need_bytes(uint32_t n, uint64_t m, uint32_t h, const hoTuning* tune, Plan* p) const {
+    if (!make_plan(n, m, h, tune, true, p, cap_factor)) return 0;
+    return p->total;
+  }
+
+  hoStatus submit(const Request& r0, size_t* id) {
+    Request r = r0;
+    if (!need_bytes(r.n, r.m, r.h, r.has_tune ? &r.tune : nullptr, &r.plan)) return HO_ERR_INVALID_ARG;
+    if (r.plan.h > hmax) return HO_ERR_INVALID_ARG;
+    if (r.plan.total > bytes - engine_header_bytes(S)) return HO_ERR_BUDGET;
+    reqs.push_back(r);
+    *id = reqs.size() - 1;
+    queue.push_back(*id);
+    return HO_OK;
+  }
+
+  // Admit queued requests (in queue order) while a slot and memory are free.
+  hoStatus admit(hipEvent_t sup0 = nullptr, hipEvent_t sup1 = nullptr) {
+    for (size_t qi = 0; qi < queue.size();) {
+      Request& r = reqs[queue[qi]];
+      int slot = -1;
+      for (uint32_t i = 0; i < S; ++i)
+        if (slot_req[i] < 0) { slot = (int)i; break; }
+      if (slot < 0) return HO_OK;
+      size_t off;
+      if (!pool.alloc(r.plan.total, &off)) {
+        ++qi;  // a later, smaller request may still fit
+        continue;
+      }
+      r.slot = slot;
+      r.off = off;
+      r.state = 1;
+      slot_req[slot] = (int)queue[qi];
+      queue.erase(queue.begin() + qi);
+      Dev d = carve(r.plan, (void*)(base + off), r.rp, r.ci, r.t, r.rho);
+      d.self = devs_d + slot;
+      d.status = status_d + 2 * slot;
+      d.nminpart = g.jump;
+      if (r.has_tune) d.serial = r.tune.flags & (HO_FLAG_SERIAL_LEVELS | HO_FLAG_SERIAL_SUPPORT);
+      slot_dev[slot] = d;
+      slot_since[slot] = steps;
+      HOCHK(start_slot(d, r.has_tune ? &r.tune : nullptr, sup0, sup1));
+    }
+    return HO_OK;
+  }
+
+  hoStatus start_slot(const Dev& d, const hoTuning* tune, hipEvent_t sup0 = nullptr,
+                      hipEvent_t sup1 = nullptr) {
+    const unsigned T = 256;
+    hipLaunchKernelGGL(k_fill32, dim3(grid_for(d.m, T)), dim3(T), 0, s, d.t, (size_t)d.m, 0u);
+    for (uint32_t j = 1; j <= d.h; ++j)
+      if (d.Dm[j])
+        hipLaunchKernelGGL(k_fill64, dim3(grid_for((size_t)d.n * d.W, T)), dim3(T), 0, s, d.Dm[j],
+                           (size_t)d.n * d.W, 0ull);
+    HOCHK(run_init(d, d.sup, tune, s, sup0, sup1));
+    const size_t i = (size_t)(d.self - devs_d);
+    dev_h[i] = d;
+    HIPCHK(hipMemcpyAsync(d.self, &dev_h[i], sizeof(Dev), hipMemcpyHostToDevice, s));
+    hipLaunchKernelGGL(k_post_init, dim3(1), dim3(64), 0, s, d);
+    HIPCHK(hipGetLastError());
+    return HO_OK;
+  }
+
+  hoStatus ensure_graphs() {
+    if (exec[0]) return HO_OK;
+    int dev = 0;
+    HIPCHK(hipGetDevice(&dev));
+    const GraphKey key{dev, devs_d, S, hmax, g.jump, g.mark, g.level, g.support};
+    {
+      std::lock_guard<std::mutex> lk(g_graph_mu);
+      for (auto& e : g_graph_cache)
+        if (e.key == key) {
+          for (int i = 0; i < 3; ++i) exec[i] = e.exec[i];
+          return HO_OK;
+        }
+    }
+    hipStream_t cap;
+    HIPCHK(hipStreamCreateWithFlags(&cap, hipStreamNonBlocking));
+    const uint32_t sizes[3] = {4, 32, 128};
+    hoStatus st = HO_OK;
+    for (int i = 0; i < 3 && st == HO_OK; ++i) {
+      hipGraph_t graph;
+      if (hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal) != hipSuccess) {
+        st = HO_ERR_HIP;
+        break;
+      }
+      for (uint32_t k = 0; k < sizes[i]; ++k) launch_step(devs_d, S, hmax, g, cap);
+      if (hipStreamEndCapture(cap, &graph) != hipSuccess) {
+        st = HO_ERR_HIP;
+        break;
+      }
+      if (hipGraphInstantiate(&exec[i], graph, nullptr, nullptr, 0) != hipSuccess) st = HO_ERR_HIP;
+      (void)hipGraphDestroy(graph);
+    }
+    (void)hipStreamDestroy(cap);
+    if (st != HO_OK) return st;
+    std::lock_guard<std::mutex> lk(g_graph_mu);
+    if (g_graph_cache.size() < GRAPH_CACHE) {
+      GraphCacheEntry e{key, {exec[0], exec[1], exec[2]}};
+      g_graph_cache.push_back(e);
+    } else {
+      owns_graphs = true;
+    }
+    return HO_OK;
+  }
+
+  bool busy() const {
+    for (int r : slot_req)
+      if (r >= 0) return true;
+    return false;
+  }
+
+  // Retire finished slots seen in the status snapshot taken after graph
+  // launch `at`; returns whether an active slot halted.  A slot admitted
+  // after that launch was enqueued is not described by the snapshot.
+  bool retire(const uint32_t* st, uint64_t at) {
+    bool halted = false;
+    for (uint32_t i = 0; i < S; ++i) {
+      const int ri = slot_req[i];
+      if (ri < 0 || at < slot_since[i]) continue;
+      if (st[2 * i + 1]) halted = true;
+      if (!st[2 * i]) continue;
+      Request& r = reqs[ri];
+      r.state = 2;
+      r.result = st[2 * i] == 2 ? HO_ERR_BAD_CSR : HO_OK;
+      // park the slot before its memory can be handed to another request:
+      // replays already in flight still read the old, finished control block
+      if (hipMemcpyAsync(devs_d + i, &idle_h[i], sizeof(Dev), hipMemcpyHostToDevice, s) !=
+          hipSuccess)
+        copy_failed = true;
+      pool.release(r.off, r.plan.total);
+      slot_req[i] = -1;
+    }
+    return halted;
+  }
+
+  // Finish the current round of every halted slot from the host.
+  hoStatus recover_halts() {
+    HIPCHK(hipStreamSynchronize(s));
+    StepTimer tm;
+    for (uint32_t i = 0; i < S; ++i) {
+      if (slot_req[i] < 0) continue;
+      Ctl c;
+      HOCHK(read_ctl(slot_dev[i], &c, s));
+      if (!c.halt) continue;
+      HOCHK(steps_host(slot_dev[i], g, s, c.halt_step, true, tm));
+    }
+    return HO_OK;
+  }
+
+  // Replay the step graph until no slot is active and the queue is empty
+  // (or max_launches replays have been launched), two replays in flight, the
+  // slots' status words copied to pinned memory after each.
+  hoStatus run(uint64_t max_launches = UINT64_MAX) {
+    HOCHK(admit());
+    if (!busy()) return HO_OK;
+    HOCHK(ensure_graphs());
+    uint64_t launched = 0;
+    uint64_t buf_at[2] = {0, 0};
+    int head = 0, inflight = 0;
+    while (true) {
+      while (inflight < 2 && busy() && launched < max_launches) {
+        const int buf = (head + inflight) & 1;
+        const int which = plain ? (steps == 0 ? 0 : steps < 4 ? 1 : 2) : (queue.empty() ? 2 : 1);
+        HIPCHK(hipGraphLaunch(exec[which], s));
+        HIPCHK(hipMemcpyAsync(hstat + 2 * S * buf, status_d, 8ull * S, hipMemcpyDeviceToHost, s));
+        HIPCHK(hipEventRecord(ev[buf], s));
+        buf_at[buf] = steps++;
+        ++launched;
+        ++inflight;
+      }
+      if (inflight == 0) break;
+      HIPCHK(hipEventSynchronize(ev[head]));
+      const bool halted = retire(hstat + 2 * S * head, buf_at[head]);
+      if (copy_failed) return HO_ERR_HIP;
+      head ^= 1;
+      --inflight;
+      if (halted) {
+        HIPCHK(hipStreamSynchronize(s));
+        inflight = 0;
+        head = 0;
+        HOCHK(recover_halts());
+      }
+      HOCHK(admit());
+    }
+    HIPCHK(hipStreamSynchronize(s));
+    return HO_OK;
+  }
+};
+
+// Debug / stats form of the plain path: every round driven from the host.
+hoStatus run_rounds_host(const Dev& d, const RoundGrid& g, hipStream_t s, bool timed, double* kms,
+                         uint64_t* klaunch) {
   const unsigned T = 256;
   const Dev* dp = d.self;
   StepTimer tm;
@@ -460,6 +731,11 @@ hoStatus check_common(const uint32_t* rp, const uint32_t* ci, uint32_t n, uint64
 
 using namespace hotruss;
 
+struct hoSession {
+  Engine eng;
+  std::mutex mu;
+};
+
 extern "C" {
 
 const char* hoStatusString(hoStatus s) {
@@ -481,7 +757,7 @@ const char* hoStatusString(hoStatus s) {
 size_t hoTrussWorkspaceBytes(uint32_t n, uint64_t m, uint32_t h, const hoTuning* tune) {
   Plan p;
   if (!make_plan(n, m, h, tune, true, &p)) return 0;
-  return p.total;
+  return p.total + engine_header_bytes(1) + ALIGN;
 }
 
 hoStatus hoTrussHSupport(const uint32_t* row_ptr, const uint32_t* col_idx, uint32_t n, uint64_t m,
@@ -513,15 +789,20 @@ hoStatus hoTrussDecompose(const uint32_t* row_ptr, const uint32_t* col_idx, uint
   }
   Plan p;
   if (!make_plan(n, m, h, tune, true, &p)) return HO_ERR_INVALID_ARG;
-  if (workspace_bytes < p.total) return HO_ERR_WORKSPACE;
-  Dev d = carve(p, workspace, row_ptr, col_idx, out_trussness, out_round);
-  if (tune) d.serial = tune->flags & (HO_FLAG_SERIAL_LEVELS | HO_FLAG_SERIAL_SUPPORT);
+  if (workspace_bytes < p.total + engine_header_bytes(1) + ALIGN) return HO_ERR_WORKSPACE;
   const bool stats = tune && (tune->flags & HO_FLAG_STATS);
-  if (stats) {
-    d.spart = stats_part_base;
-    HIPCHK(hipMemsetAsync(d.spart, 0, 4ull * NSTAT * STAT_GRID, stream));
-  }
   const bool host_loop = stats || (tune && (tune->flags & HO_FLAG_HOST_LOOP));
+  const RoundGrid g = plain_grid(m, tune);
+  Engine eng;
+  HOCHK(eng.init(workspace, workspace_bytes, 1, p.h, g, stream, true));
+  Request r;
+  r.rp = row_ptr; r.ci = col_idx; r.n = n; r.m = m; r.h = h;
+  r.t = out_trussness; r.rho = out_round;
+  if (tune) { r.tune = *tune; r.has_tune = true; }
+  size_t id;
+  st = eng.submit(r, &id);
+  if (st == HO_ERR_BUDGET) return HO_ERR_WORKSPACE;
+  HOCHK(st);
   hoStats out{};
   hipEvent_t ev0, ev1, es0 = nullptr, es1 = nullptr;
   HIPCHK(hipEventCreate(&ev0));
@@ -531,40 +812,39 @@ hoStatus hoTrussDecompose(const uint32_t* row_ptr, const uint32_t* col_idx, uint
     HIPCHK(hipEventCreate(&es1));
   }
   HIPCHK(hipEventRecord(ev0, stream));
-  const unsigned T = 256;
-  // outputs and change marks start at zero
-  hipLaunchKernelGGL(k_fill32, dim3(grid_for(d.m, T)), dim3(T), 0, stream, d.t, (size_t)d.m, 0u);
-  for (uint32_t j = 1; j <= d.h; ++j)
-    if (d.Dm[j])
-      hipLaunchKernelGGL(k_fill64, dim3(grid_for((size_t)d.n * d.W, T)), dim3(T), 0, stream,
-                         d.Dm[j], (size_t)d.n * d.W, 0ull);
-  st = run_init(d, d.sup, tune, stream, es0, es1);
-  if (st != HO_OK) return st;
-  Ctl c;
-  st = read_ctl(d, &c, stream);
-  if (st != HO_OK) return st;
-  if (c.err) return HO_ERR_BAD_CSR;
-  if (stats) {
-    float ms = 0;
-    HIPCHK(hipEventElapsedTime(&ms, es0, es1));
-    out.kernel_ms[KT_SUPINIT] = ms;
-    out.kernel_launches[KT_SUPINIT] = 1;
-    (void)hipEventDestroy(es0);
-    (void)hipEventDestroy(es1);
+  if (host_loop) {
+    HOCHK(eng.admit(es0, es1));
+    Dev d = eng.slot_dev[0];
+    Ctl c;
+    HOCHK(read_ctl(d, &c, stream));
+    if (c.err) return HO_ERR_BAD_CSR;
+    if (stats) {
+      float ms = 0;
+      HIPCHK(hipEventElapsedTime(&ms, es0, es1));
+      out.kernel_ms[KT_SUPINIT] = ms;
+      out.kernel_launches[KT_SUPINIT] = 1;
+      (void)hipEventDestroy(es0);
+      (void)hipEventDestroy(es1);
+      d.spart = eng.spart_d;
+      HIPCHK(hipMemsetAsync(d.spart, 0, 4ull * NSTAT * STAT_GRID, stream));
+      HIPCHK(hipMemcpyAsync(d.self, &d, sizeof(Dev), hipMemcpyHostToDevice, stream));
+    }
+    HOCHK(run_rounds_host(d, g, stream, stats, out.kernel_ms, out.kernel_launches));
+  } else {
+    HOCHK(eng.run());
+    if (eng.reqs[id].state != 2) return HO_ERR_INTERNAL;
+    HOCHK(eng.reqs[id].result);
   }
-  HIPCHK(hipMemcpyAsync(d.self, &d, sizeof(Dev), hipMemcpyHostToDevice, stream));
-  st = host_loop ? run_rounds_host(d, tune, stream, stats, out.kernel_ms, out.kernel_launches)
-                 : run_rounds_graph(d, tune, stream);
-  if (st != HO_OK) return st;
   HIPCHK(hipEventRecord(ev1, stream));
   HIPCHK(hipEventSynchronize(ev1));
   float ms = 0;
   HIPCHK(hipEventElapsedTime(&ms, ev0, ev1));
   (void)hipEventDestroy(ev0);
   (void)hipEventDestroy(ev1);
-  st = read_ctl(d, &c, stream);
-  if (st != HO_OK) return st;
-  if (c.err) return HO_ERR_INTERNAL;
+  Ctl c;
+  HOCHK(read_ctl(eng.slot_dev[0], &c, stream));
+  if (c.err) return HO_ERR_BAD_CSR;
+  if (!c.done) return HO_ERR_INTERNAL;
   out.rounds = c.r;
   out.levels = c.levels;
   out.events = c.events;
@@ -581,17 +861,186 @@ hoStatus hoTrussLastStats(hoStats* out) {
   return HO_OK;
 }
 
-size_t hoTrussBatchedWorkspaceBytes(const uint64_t* vtx_off, const uint64_t* edge_off,
-                                    const uint32_t* h, uint32_t B, const hoTuning* tune) {
-  (void)vtx_off; (void)edge_off; (void)h; (void)B; (void)tune;
-  return 0;
+// ----------------------------------------------------------------- batched
+static uint32_t batch_slots(uint32_t B, const hoTuning* tune) {
+  (void)tune;
+  return std::max(1u, std::min(B, 256u));
 }
 
-hoStatus hoTrussDecomposeBatched(const uint32_t*, const uint32_t*, const uint64_t*,
-                                 const uint64_t*, const uint64_t*, const uint32_t*, uint32_t,
-                                 uint32_t*, uint32_t*, void*, size_t, const hoTuning*,
-                                 hipStream_t) {
-  return HO_ERR_INVALID_ARG;
+size_t hoTrussBatchedWorkspaceBytes(const uint64_t* vtx_off, const uint64_t* edge_off,
+                                    const uint32_t* h, uint32_t B, const hoTuning* tune) {
+  if (!vtx_off || !edge_off || !h || B == 0) return 0;
+  // every graph resident at once, capped at what the widest graphs need
+  // when 64 run together; any workspace that holds the largest graph works
+  std::vector<size_t> need(B);
+  size_t sum = 0, mx = 0;
+  for (uint32_t g = 0; g < B; ++g) {
+    Plan p;
+    const uint32_t n = (uint32_t)(vtx_off[g + 1] - vtx_off[g]);
+    const uint64_t m = edge_off[g + 1] - edge_off[g];
+    if (m == 0) continue;
+    if (!make_plan(n, m, h[g], tune, true, &p, 16)) return 0;
+    need[g] = up(p.total);
+    sum += need[g];
+    mx = std::max(mx, need[g]);
+  }
+  std::sort(need.begin(), need.end(), std::greater<size_t>());
+  size_t top = 0;
+  for (uint32_t g = 0; g < B && g < 64; ++g) top += need[g];
+  return std::min(sum, top) + engine_header_bytes(batch_slots(B, tune)) + 2 * ALIGN;
+}
+
+hoStatus hoTrussDecomposeBatched(const uint32_t* row_ptr_cat, const uint32_t* col_idx_cat,
+                                 const uint64_t* vtx_off, const uint64_t* adj_off,
+                                 const uint64_t* edge_off, const uint32_t* h, uint32_t B,
+                                 uint32_t* out_t_cat, uint32_t* out_round_cat, void* workspace,
+                                 size_t workspace_bytes, const hoTuning* tune,
+                                 hipStream_t stream) {
+  if (!vtx_off || !adj_off || !edge_off || !h) return HO_ERR_INVALID_ARG;
+  if (B == 0) return HO_OK;
+  if (!row_ptr_cat || !col_idx_cat || !out_t_cat || !workspace) return HO_ERR_INVALID_ARG;
+  uint32_t hmax = 1;
+  for (uint32_t g = 0; g < B; ++g) {
+    if (h[g] == 0) return HO_ERR_INVALID_ARG;
+    const uint64_t n = vtx_off[g + 1] - vtx_off[g];
+    if (adj_off[g + 1] - adj_off[g] != 2 * (edge_off[g + 1] - edge_off[g])) return HO_ERR_INVALID_ARG;
+    hmax = std::max<uint32_t>(hmax, std::min<uint64_t>(h[g], n > 1 ? n - 1 : 1));
+  }
+  if (hmax > HMAX) return HO_ERR_INVALID_ARG;
+  // longest first: graphs ordered by workspace (the ball store grows as n^2 h)
+  uint32_t S = batch_slots(B, tune);
+  std::vector<std::pair<size_t, uint32_t>> order;
+  size_t largest = 0;
+  for (uint32_t g = 0; g < B; ++g) {
+    const uint64_t m = edge_off[g + 1] - edge_off[g];
+    if (m == 0) continue;
+    Plan p;
+    const uint32_t n = (uint32_t)(vtx_off[g + 1] - vtx_off[g]);
+    if (!make_plan(n, m, h[g], tune, true, &p, 16)) return HO_ERR_INVALID_ARG;
+    order.push_back({p.total, g});
+    largest = std::max(largest, up(p.total));
+  }
+  if (order.empty()) return HO_OK;
+  // fewer slots (a smaller header) when the workspace holds little more than
+  // the largest graph
+  while (S > 1 && workspace_bytes < largest + engine_header_bytes(S) + ALIGN) S = S / 2;
+  if (workspace_bytes < largest + engine_header_bytes(S) + ALIGN) return HO_ERR_WORKSPACE;
+  Engine eng;
+  eng.cap_factor = 16;
+  HOCHK(eng.init(workspace, workspace_bytes, S, hmax, batch_grid(S, tune), stream, false));
+  std::sort(order.begin(), order.end(), std::greater<std::pair<size_t, uint32_t>>());
+  std::vector<size_t> ids;
+  for (auto& og : order) {
+    const uint32_t g = og.second;
+    Request r;
+    r.rp = row_ptr_cat + vtx_off[g] + g;
+    r.ci = col_idx_cat + adj_off[g];
+    r.n = (uint32_t)(vtx_off[g + 1] - vtx_off[g]);
+    r.m = edge_off[g + 1] - edge_off[g];
+    r.h = h[g];
+    r.t = out_t_cat + edge_off[g];
+    r.rho = out_round_cat ? out_round_cat + edge_off[g] : nullptr;
+    if (tune) { r.tune = *tune; r.has_tune = true; }
+    size_t id;
+    const hoStatus st = eng.submit(r, &id);
+    if (st == HO_ERR_BUDGET) return HO_ERR_WORKSPACE;  // a graph that can never fit
+    HOCHK(st);
+    ids.push_back(id);
+  }
+  while (!eng.queue.empty() || eng.busy()) {
+    HOCHK(eng.run());
+    if (!eng.busy() && !eng.queue.empty()) return HO_ERR_WORKSPACE;
+  }
+  for (size_t id : ids)
+    if (eng.reqs[id].result != HO_OK) return eng.reqs[id].result;
+  return HO_OK;
+}
+
+// ----------------------------------------------------------------- sessions
+hoStatus hoSessionCreate(void* pool, size_t pool_bytes, uint32_t max_slots, uint32_t max_h,
+                         hipStream_t stream, hoSession** out) {
+  if (!pool || !out || max_slots == 0 || max_slots > 4096 || max_h == 0 || max_h > HMAX)
+    return HO_ERR_INVALID_ARG;
+  hoSession* ss = new (std::nothrow) hoSession();
+  if (!ss) return HO_ERR_INVALID_ARG;
+  ss->eng.cap_factor = 16;
+  hoStatus st = ss->eng.init(pool, pool_bytes, max_slots, max_h, batch_grid(max_slots, nullptr),
+                             stream, false);
+  if (st != HO_OK) {
+    delete ss;
+    return st;
+  }
+  *out = ss;
+  return HO_OK;
+}
+
+hoStatus hoSubmit(hoSession* ss, const uint32_t* row_ptr, const uint32_t* col_idx, uint32_t n,
+                  uint64_t m, uint32_t h, uint32_t* out_trussness, uint32_t* out_round,
+                  uint64_t* out_ticket) {
+  if (!ss || !out_ticket) return HO_ERR_INVALID_ARG;
+  hoStatus st = check_common(row_ptr, col_idx, n, m, h, out_trussness, (void*)1);
+  if (st != HO_OK) return st;
+  std::lock_guard<std::mutex> lk(ss->mu);
+  Request r;
+  r.rp = row_ptr; r.ci = col_idx; r.n = n; r.m = m; r.h = h;
+  r.t = out_trussness; r.rho = out_round;
+  size_t id;
+  if (m == 0) {  // nothing to compute: finished at once
+    r.state = 2;
+    ss->eng.reqs.push_back(r);
+    *out_ticket = ss->eng.reqs.size() - 1;
+    return HO_OK;
+  }
+  st = ss->eng.submit(r, &id);
+  if (st != HO_OK) return st;
+  *out_ticket = id;
+  return HO_OK;
+}
+
+hoStatus hoSessionProgress(hoSession* ss, uint32_t max_graph_launches, uint32_t* active,
+                           uint32_t* queued) {
+  if (!ss) return HO_ERR_INVALID_ARG;
+  std::lock_guard<std::mutex> lk(ss->mu);
+  hoStatus st = ss->eng.run(max_graph_launches ? max_graph_launches : UINT64_MAX);
+  if (active) {
+    uint32_t a = 0;
+    for (int r : ss->eng.slot_req) a += r >= 0;
+    *active = a;
+  }
+  if (queued) *queued = (uint32_t)ss->eng.queue.size();
+  return st;
+}
+
+hoStatus hoPoll(hoSession* ss, uint64_t ticket, int* done) {
+  if (!ss || !done) return HO_ERR_INVALID_ARG;
+  std::lock_guard<std::mutex> lk(ss->mu);
+  if (ticket >= ss->eng.reqs.size()) return HO_ERR_NOT_FOUND;
+  const Request& r = ss->eng.reqs[ticket];
+  *done = r.state >= 2;
+  if (r.state == 3) return HO_ERR_CANCELLED;
+  return r.state == 2 ? r.result : HO_OK;
+}
+
+hoStatus hoCancel(hoSession* ss, uint64_t ticket) {
+  if (!ss) return HO_ERR_INVALID_ARG;
+  std::lock_guard<std::mutex> lk(ss->mu);
+  if (ticket >= ss->eng.reqs.size()) return HO_ERR_NOT_FOUND;
+  Request& r = ss->eng.reqs[ticket];
+  if (r.state != 0) return HO_ERR_BUSY;  // only queued requests can be cancelled
+  r.state = 3;
+  auto& q = ss->eng.queue;
+  q.erase(std::remove(q.begin(), q.end(), (size_t)ticket), q.end());
+  return HO_OK;
+}
+
+hoStatus hoSessionDestroy(hoSession* ss) {
+  if (!ss) return HO_ERR_INVALID_ARG;
+  {
+    std::lock_guard<std::mutex> lk(ss->mu);
+    (void)hipStreamSynchronize(ss->eng.s);
+  }
+  delete ss;
+  return HO_OK;
 }
 
 }  // extern "C"

@@ -98,6 +98,8 @@ struct Dev {
   Ctl* ctl;
   Dev* self;               // device-resident copy of this struct (round kernels read it)
   uint32_t* spart;         // stats mode: per-workgroup counters [NSTAT][STAT_GRID], else null
+  uint32_t* status;        // this slot's {done, halt} words in the engine's status array
+                           // (done: 1 finished, 2 malformed CSR)
 };
 
 __device__ __forceinline__ uint32_t lane_id() { return threadIdx.x & (WAVE - 1); }

@@ -331,8 +331,8 @@ __device__ void record_events(const Dev& d, uint32_t j, uint32_t p, uint32_t cnt
 }
 
 // ---- K1: level-jump minimum and clearing of overflowed change marks ----
-__global__ void __launch_bounds__(256) k_jump_min(const Dev* __restrict__ dp) {
-  const Dev& d = *dp;
+__global__ void __launch_bounds__(256) k_jump_min(const Dev* __restrict__ devs) {
+  const Dev& d = devs[blockIdx.y];
   __shared__ uint32_t smin[4];
   const Ctl* c = d.ctl;
   if (c->done || c->halt) return;
@@ -396,8 +396,8 @@ __device__ void mark_edge(const Dev& d, const RoundCtx& rc, bool valid, uint32_t
   }
 }
 
-__global__ void __launch_bounds__(256) k_mark(const Dev* __restrict__ dp) {
-  const Dev& d = *dp;
+__global__ void __launch_bounds__(256) k_mark(const Dev* __restrict__ devs) {
+  const Dev& d = devs[blockIdx.y];
   Ctl* c = d.ctl;
   if (c->done || c->halt) return;
   RoundCtx rc = round_ctx(c);
@@ -485,8 +485,9 @@ __device__ uint32_t block_scan_cap(const uint32_t* v, uint32_t* out, uint32_t n,
 // the pair's probes (the live neighbours y of its lower-degree endpoint a,
 // each checked against the other endpoint's (j-1)-ball) are laid out flat
 // over all threads of the workgroup.  Pairs with no witness leave the ball.
-__global__ void __launch_bounds__(LV_THREADS) k_level(const Dev* __restrict__ dp, uint32_t j) {
-  const Dev& d = *dp;
+__global__ void __launch_bounds__(LV_THREADS) k_level(const Dev* __restrict__ devs, uint32_t j) {
+  const Dev& d = devs[blockIdx.y];
+  if (j > d.h) return;  // this slot's graph has fewer levels
   __shared__ uint32_t cx[LV_CAP], cw[LV_CAP], cb[LV_CAP], cbeg[LV_CAP], cdeg[LV_CAP],
       coff[LV_CAP];
   __shared__ uint32_t cflag[LV_CAP];
@@ -500,6 +501,7 @@ __global__ void __launch_bounds__(LV_THREADS) k_level(const Dev* __restrict__ dp
     if (blockIdx.x == 0 && threadIdx.x == 0) {
       c->halt = 1;
       c->halt_step = j;
+      d.status[1] = 1;
     }
     return;
   }
@@ -675,8 +677,8 @@ __global__ void __launch_bounds__(LV_THREADS) k_level(const Dev* __restrict__ dp
 // Top-level event (a -> w): every live edge (a,b) that had w as a common
 // h-neighbour loses it.  Old/new rule: w counts against (a,b) if it was in
 // b's old ball when a < b, and in b's new ball when a > b (see the header).
-__global__ void __launch_bounds__(256) k_support(const Dev* __restrict__ dp) {
-  const Dev& d = *dp;
+__global__ void __launch_bounds__(256) k_support(const Dev* __restrict__ devs) {
+  const Dev& d = devs[blockIdx.y];
   Ctl* c = d.ctl;
   if (c->done) return;
   const uint32_t list = d.h + 1;
@@ -685,6 +687,7 @@ __global__ void __launch_bounds__(256) k_support(const Dev* __restrict__ dp) {
     if (blockIdx.x == 0 && threadIdx.x == 0) {
       c->halt = 1;
       c->halt_step = list;
+      d.status[1] = 1;
     }
     return;
   }
@@ -755,8 +758,8 @@ __global__ void k_stats_fold(const Dev* __restrict__ dp, uint32_t first, uint32_
 }
 
 // ---- K5: end of round ------------------------------------------------------
-__global__ void k_advance(const Dev* __restrict__ dp) {
-  const Dev& d = *dp;
+__global__ void k_advance(const Dev* __restrict__ devs) {
+  const Dev& d = devs[blockIdx.y];
   if (blockIdx.x != 0 || threadIdx.x != 0) return;
   Ctl* c = d.ctl;
   if (c->done || c->halt) return;
@@ -780,7 +783,20 @@ __global__ void k_advance(const Dev* __restrict__ dp) {
   c->r += 1;
   c->nR = c->nPush;
   c->nPush = 0;
-  if (c->live == 0) c->done = 1;
+  if (c->live == 0) {
+    c->done = 1;
+    d.status[0] = 1;
+  }
+}
+
+// After the initial pass of a newly admitted graph: publish its state
+// (malformed CSR: finished with error).
+__global__ void k_post_init(Dev d) {
+  if (blockIdx.x != 0 || threadIdx.x != 0) return;
+  Ctl* c = d.ctl;
+  if (c->err) c->done = 1;
+  d.status[0] = c->err ? 2u : (c->done ? 1u : 0u);
+  d.status[1] = 0;
 }
 
 }  // namespace hotruss

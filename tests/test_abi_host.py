@@ -65,3 +65,65 @@ def test_argument_errors_return_before_device_work(ht):
     s = ht._lib.Stats()
     assert lib.hoTrussLastStats(None) == -1
     assert lib.hoTrussLastStats(C.byref(s)) == 0
+
+
+def test_batched_argument_errors_return_before_device_work(ht):
+    import numpy as np
+    lib = ht.lib
+    nul = None
+    fake = C.c_void_p(0x1000)
+    vo = np.array([0, 10, 30], dtype=np.uint64)
+    ao = np.array([0, 20, 60], dtype=np.uint64)
+    eo = np.array([0, 10, 30], dtype=np.uint64)
+    h = np.array([2, 3], dtype=np.uint32)
+    P = lambda a: a.ctypes.data  # noqa: E731
+    # no graphs: a no-op success; missing offset arrays: invalid
+    assert lib.hoTrussDecomposeBatched(nul, nul, P(vo), P(ao), P(eo), P(h), 0, nul, nul, nul,
+                                       0, nul, nul) == 0
+    assert lib.hoTrussDecomposeBatched(fake, fake, nul, P(ao), P(eo), P(h), 2, fake, nul, fake,
+                                       1 << 30, nul, nul) == -1
+    # h == 0 in one graph
+    h0 = np.array([2, 0], dtype=np.uint32)
+    assert lib.hoTrussDecomposeBatched(fake, fake, P(vo), P(ao), P(eo), P(h0), 2, fake, nul,
+                                       fake, 1 << 30, nul, nul) == -1
+    # adjacency and edge offsets disagree (2m_g != adj_off[g+1]-adj_off[g])
+    bad = np.array([0, 20, 58], dtype=np.uint64)
+    assert lib.hoTrussDecomposeBatched(fake, fake, P(vo), P(bad), P(eo), P(h), 2, fake, nul,
+                                       fake, 1 << 30, nul, nul) == -1
+    # workspace below the largest graph's share
+    assert lib.hoTrussDecomposeBatched(fake, fake, P(vo), P(ao), P(eo), P(h), 2, fake, nul,
+                                       fake, 4096, nul, nul) == -3
+
+
+def test_batched_workspace_query(ht):
+    import numpy as np
+    # 100 equal graphs: the query covers the 64 largest at once, so it grows
+    # with B up to 64 and not beyond
+    def q(B, n=1000, m=4000, h=2):
+        vo = np.arange(B + 1, dtype=np.uint64) * n
+        eo = np.arange(B + 1, dtype=np.uint64) * m
+        return ht.batched_workspace_bytes(vo, eo, np.full(B, h, np.uint32))
+    one = ht.workspace_bytes(1000, 4000, 2)
+    assert q(1) > 0
+    assert q(1) < one  # smaller event and item lists than the plain path
+    assert q(8) > 7 * q(1) // 2
+    assert q(64) == q(100) or abs(q(64) - q(100)) < 1 << 20
+    assert q(0) == 0
+
+
+def test_session_argument_errors(ht):
+    lib = ht.lib
+    nul = None
+    out = C.c_void_p()
+    fake = C.c_void_p(0x1000)
+    assert lib.hoSessionCreate(nul, 1 << 20, 4, 2, nul, C.byref(out)) == -1
+    assert lib.hoSessionCreate(fake, 1 << 20, 0, 2, nul, C.byref(out)) == -1
+    assert lib.hoSessionCreate(fake, 1 << 20, 4, 0, nul, C.byref(out)) == -1
+    assert lib.hoSessionCreate(fake, 1 << 20, 4, 17, nul, C.byref(out)) == -1
+    t = C.c_uint64()
+    d = C.c_int()
+    assert lib.hoSubmit(nul, fake, fake, 10, 5, 2, fake, nul, C.byref(t)) == -1
+    assert lib.hoSessionProgress(nul, 0, nul, nul) == -1
+    assert lib.hoPoll(nul, 0, C.byref(d)) == -1
+    assert lib.hoCancel(nul, 0) == -1
+    assert lib.hoSessionDestroy(nul) == -1
