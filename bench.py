@@ -6,6 +6,17 @@ power-law graph, n = 100,000, average degree 10, exponent 2.5, seed 1, h = 2.
 
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload NAME]
 
+Two more workloads measure the multi-graph forms:
+  --workload batched   512 preferential-attachment graphs with planted
+                       cliques (n ~ U[1000, 50000], h in {2, 3}) in one
+                       batched call; graphs/s against a loop of single-graph
+                       calls on one stream and on four streams, results
+                       compared bit for bit
+  --workload serve     a Poisson stream of Chung-Lu requests over size classes
+                       through a session with a device-memory budget;
+                       p50/p99 latency and graphs/s at fixed fractions of the
+                       measured capacity
+
 Prints one JSON line.  Only one GPU is used; --gpus above 1 exits with a
 message.
 """
@@ -103,12 +114,226 @@ def cpu_baseline(workload: str):
                       f"re-evaluates every live edge each round, so its rate falls as graphs grow"}
 
 
+def _log(msg: str) -> None:
+    """Progress of the long multi-graph runs, on stderr (the JSON line is stdout)."""
+    print(f"[bench {time.strftime('%H:%M:%S')}] {msg}", file=sys.stderr, flush=True)
+
+
+def _gen_pool(fn, specs, workers: int):
+    """Generate graphs in worker processes (forked before any GPU use)."""
+    import multiprocessing as mp
+    if workers <= 1:
+        return [fn(x) for x in specs]
+    with mp.get_context("fork").Pool(workers) as pool:
+        return pool.map(fn, specs, chunksize=1)
+
+
+def _workers() -> int:
+    return max(1, min(16, len(os.sched_getaffinity(0))))
+
+
+def run_batched(args) -> dict:
+    """Batched call against loops of single-graph calls (one and four streams)."""
+    from graphgen import concat
+    specs = W.d4_specs()[:args.graphs]  # a prefix of the full 512-graph draw
+    gs = _gen_pool(W.d4_graph, specs, _workers())
+    _log(f"generated {len(gs)} graphs, sum m = {sum(g.m for g in gs)}")
+    hs = np.array([s[2] for s in specs], dtype=np.uint32)
+    b = concat(gs, hs)
+    import threading
+    import torch
+    import paper_2411_06405_amd as ht
+    dev = torch.device("cuda:0")
+    rp = torch.from_numpy(b.row_ptr_cat.view(np.int32)).to(dev)
+    ci = torch.from_numpy(b.col_idx_cat.view(np.int32)).to(dev)
+    vo, ao, eo = (b.vtx_off.astype(np.int64), b.adj_off.astype(np.int64),
+                  b.edge_off.astype(np.int64))
+    B, mt = b.B, int(eo[-1])
+    wsb = ht.batched_workspace_bytes(b.vtx_off, b.edge_off, b.h)
+    ws = torch.empty(wsb, dtype=torch.uint8, device=dev)
+
+    def batched():
+        return ht.decompose_batched(rp, ci, b.vtx_off, b.adj_off, b.edge_off, b.h,
+                                    workspace=ws, device=dev)
+    for i in range(args.warmup):
+        batched()
+        torch.cuda.synchronize()
+        _log(f"batched warm-up {i + 1}/{args.warmup} done")
+    t0 = time.perf_counter()
+    for i in range(args.steps):
+        tb, rb = batched()
+        torch.cuda.synchronize()
+        _log(f"batched step {i + 1}/{args.steps}: {time.perf_counter() - t0:.2f} s so far")
+    t_batch = (time.perf_counter() - t0) / max(args.steps, 1)
+    del ws
+    torch.cuda.empty_cache()
+
+    # single-graph calls, one graph after another on `nstreams` streams (one
+    # host thread and one workspace per stream)
+    n_ = [int(vo[g + 1] - vo[g]) for g in range(B)]
+    wmax = max(ht.workspace_bytes(n_[g], int(eo[g + 1] - eo[g]), int(hs[g])) for g in range(B))
+    tp = torch.empty(max(mt, 1), dtype=torch.int32, device=dev)
+    rp_out = torch.empty(max(mt, 1), dtype=torch.int32, device=dev)
+
+    def plain_loop(nstreams: int) -> float:
+        streams = [torch.cuda.Stream(device=dev) for _ in range(nstreams)]
+        wss = [torch.empty(wmax, dtype=torch.uint8, device=dev) for _ in range(nstreams)]
+        order = sorted(range(B), key=lambda g: -int(eo[g + 1] - eo[g]))
+        errors = []
+
+        def worker(i):
+            try:
+                with torch.cuda.stream(streams[i]):
+                    for c, g in enumerate(order[i::nstreams]):
+                        t, r = ht.decompose(rp[vo[g] + g:vo[g + 1] + g + 1], ci[ao[g]:ao[g + 1]],
+                                            n_[g], int(hs[g]), workspace=wss[i],
+                                            stream=streams[i], device=dev)
+                        tp[eo[g]:eo[g + 1]].copy_(t)
+                        rp_out[eo[g]:eo[g + 1]].copy_(r)
+                        if i == 0 and c % 16 == 15:
+                            streams[i].synchronize()
+                            _log(f"plain x{nstreams}: stream 0 finished {c + 1} graphs")
+                    streams[i].synchronize()
+            except Exception as e:  # reported below
+                errors.append(e)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        th = [threading.Thread(target=worker, args=(i,)) for i in range(nstreams)]
+        for x in th:
+            x.start()
+        for x in th:
+            x.join()
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        if errors:
+            raise errors[0]
+        return dt
+    t_plain1 = plain_loop(1)
+    _log(f"plain loop, 1 stream: {t_plain1:.2f} s")
+    same1 = bool(torch.equal(tb, tp[:mt]) and torch.equal(rb, rp_out[:mt]))
+    t_plain4 = plain_loop(4)
+    _log(f"plain loop, 4 streams: {t_plain4:.2f} s")
+    same4 = bool(torch.equal(tb, tp[:mt]) and torch.equal(rb, rp_out[:mt]))
+    value = B / t_batch
+    return {
+        "metric": "graphs/s, batched call vs single-graph calls",
+        "value": value, "unit": "graphs/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": t_batch * 1e3, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "u32", "data": "synthetic",
+        "config": {"workload": f"{B} Barabasi-Albert graphs, n~U[1000,50000], m_attach~U{{3..8}}, "
+                               f"5 planted cliques of 8-20 vertices each, h~U{{2,3}}, seed "
+                               f"{W.D4_SEED}",
+                   "graphs": B, "sum_n": int(vo[-1]), "sum_m": mt,
+                   "workspace_gib": round(wsb / 2**30, 2)},
+        "plain_1stream_graphs_s": B / t_plain1, "plain_4stream_graphs_s": B / t_plain4,
+        "speedup_vs_plain_1stream": t_plain1 / t_batch,
+        "speedup_vs_plain_4stream": t_plain4 / t_batch,
+        "edges_per_s_batched": mt / t_batch,
+        "identical_to_plain": same1 and same4,
+    }
+
+
+def run_serve(args) -> dict:
+    """Poisson request stream through a session with a device-memory budget."""
+    specs = W.d5_request_specs(args.requests)
+    if args.max_class:
+        specs = [s if s[0] <= args.max_class else (args.max_class,) + tuple(s[1:])
+                 for s in specs]
+    gs = _gen_pool(W.d5_graph, specs, _workers())
+    _log(f"generated {len(gs)} requests, sum m = {sum(g.m for g in gs)}")
+    import torch
+    import paper_2411_06405_amd as ht
+    dev = torch.device("cuda:0")
+    budget = int(args.budget_gib * 2**30)
+    rps = [torch.from_numpy(g.row_ptr.view(np.int32)).to(dev) for g in gs]
+    cis = [torch.from_numpy(g.col_idx.view(np.int32)).to(dev) for g in gs]
+    hs = [s[3] for s in specs]
+    N = len(gs)
+    sess = ht.Session(pool_bytes=budget, max_slots=args.slots, max_h=max(hs), device=dev)
+
+    def drive(arrivals):
+        """Submit request i at arrivals[i] (seconds); return completion times and results."""
+        t0 = time.perf_counter()
+        done_at = np.full(N, np.nan)
+        tickets = [None] * N
+        nxt, pending = 0, set()
+        while nxt < N or pending:
+            now = time.perf_counter() - t0
+            while nxt < N and arrivals[nxt] <= now:
+                tickets[nxt] = sess.submit(rps[nxt], cis[nxt], gs[nxt].n, hs[nxt])
+                pending.add(nxt)
+                nxt += 1
+            if pending:
+                sess.progress(max_graph_launches=1)
+                now = time.perf_counter() - t0
+                for i in list(pending):
+                    if sess.poll(tickets[i]):
+                        done_at[i] = now
+                        pending.discard(i)
+            elif nxt < N:
+                time.sleep(max(0.0, min(arrivals[nxt] - now, 0.01)))
+        res = [sess.result(tk) for tk in tickets]
+        return done_at, res
+
+    # warm-up (graph capture, first-touch) on the smallest requests
+    small = sorted(range(N), key=lambda i: gs[i].m)[:min(8, N)]
+    for i in small:
+        sess.submit(rps[i], cis[i], gs[i].n, hs[i])
+    sess.progress()
+    # capacity: every request queued at time 0
+    _log("warm-up done")
+    done_cap, res_cap = drive(np.zeros(N))
+    capacity = N / float(np.nanmax(done_cap))
+    _log(f"capacity run: {capacity:.2f} graphs/s")
+    out = {"capacity_graphs_s": capacity, "loads": {}}
+    identical = True
+    for load in args.loads:
+        arr = W.poisson_arrivals(N, load * capacity)
+        arr = arr - arr[0]
+        done_at, res = drive(arr)
+        _log(f"load {load}: done in {float(np.nanmax(done_at)):.2f} s")
+        lat = (done_at - arr) * 1e3
+        skip = N // 20  # warm-up share of the stream
+        lat_s = lat[skip:]
+        identical &= all(np.array_equal(a[0], c[0]) and np.array_equal(a[1], c[1])
+                         for a, c in zip(res, res_cap))
+        out["loads"][str(load)] = {
+            "qps": load * capacity, "graphs_s": N / float(np.nanmax(done_at)),
+            "p50_ms": float(np.percentile(lat_s, 50)), "p99_ms": float(np.percentile(lat_s, 99)),
+            "max_ms": float(np.max(lat_s))}
+    sess.close()
+    head = out["loads"][str(args.loads[0])]
+    classes = sorted({s[0] for s in specs})
+    return {
+        "metric": "p50/p99 latency and graphs/s, served request stream",
+        "value": head["graphs_s"], "unit": "graphs/s", "n_gpus": 1, "steps": N,
+        "warmup": len(small), "ms_per_step": 1e3 / head["graphs_s"], "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "u32", "data": "synthetic",
+        "config": {"workload": f"{N} Chung-Lu requests, n in {classes}, gamma~U[2.1,2.8], "
+                               f"avg_deg~U[6,20], h~U{{2,3,4}}, Poisson arrivals seed "
+                               f"{W.D5_SEED}",
+                   "budget_gib": args.budget_gib, "slots": args.slots,
+                   "sum_m": int(sum(g.m for g in gs))},
+        "p50_ms": head["p50_ms"], "p99_ms": head["p99_ms"], **out,
+        "identical_across_runs": bool(identical),
+    }
+
+
 def main(argv=None):
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="chung_lu_100k_h2", choices=sorted(WORKLOADS))
+    ap.add_argument("--workload", default="chung_lu_100k_h2",
+                    choices=sorted(WORKLOADS) + ["batched", "serve"])
+    ap.add_argument("--graphs", type=int, default=W.D4_B, help="batched: number of graphs")
+    ap.add_argument("--requests", type=int, default=200, help="serve: number of requests")
+    ap.add_argument("--max-class", type=int, default=0,
+                    help="serve: cap the size classes at this n (0: all classes)")
+    ap.add_argument("--budget-gib", type=float, default=64.0, help="serve: device-memory budget")
+    ap.add_argument("--slots", type=int, default=64, help="serve: concurrent requests")
+    ap.add_argument("--loads", type=float, nargs="+", default=[0.5, 0.8],
+                    help="serve: arrival rates as fractions of the measured capacity")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--calibrate", action="store_true",
                     help="also copy a 256 MiB buffer (reference kernel for HBM counters)")
@@ -117,6 +342,13 @@ def main(argv=None):
         print(json.dumps({"error": "this benchmark runs on exactly one GPU; "
                                    "multi-GPU runs are not part of this build"}))
         return 2
+
+    if args.workload == "batched":
+        print(json.dumps(run_batched(args)), flush=True)
+        return 0
+    if args.workload == "serve":
+        print(json.dumps(run_serve(args)), flush=True)
+        return 0
 
     import torch
     import paper_2411_06405_amd as ht
