@@ -58,14 +58,20 @@ typedef enum {
 } hoStatus;
 
 /* Optional knobs; pass NULL for defaults.  Every setting gives the same
- * results; they only change speed and workspace size. */
+ * results; they only change speed and workspace size.  The first three tune
+ * the initial pass (edge ids, ball build, initial h-support); the autotuner
+ * in the Python package picks them per graph shape by measurement. */
 typedef struct {
-    uint32_t word_bits;       /* bitset load width per lane: 64 or 128 (0 = auto)        */
-    uint32_t dense_threshold; /* ball build: frontier degree sum above which a row is
-                                 built by OR-ing neighbour rows instead of scattering
-                                 the frontier's adjacency (0 = auto)                      */
+    uint32_t word_bits;       /* initial h-support: bitset load width per lane, 64 or 128
+                                 (0 = 64)                                                 */
+    uint32_t dense_threshold; /* level-2 ball build: a row is built bottom-up (OR of the
+                                 neighbours' level-1 rows, dense frontier) instead of
+                                 top-down (scatter of their adjacency lists, sparse
+                                 frontier) when those lists hold more than
+                                 dense_threshold/16 entries per bitset word the bottom-up
+                                 build reads, i.e. (deg(x)+1)*W words; 0 = 32            */
     uint32_t edges_per_wave;  /* initial h-support: edges sharing one wavefront, 1..16
-                                 (0 = auto)                                              */
+                                 (0 = by row width)                                      */
     uint32_t flags;           /* HO_FLAG_*                                               */
     uint32_t event_capacity;  /* per-level ball-change event list entries; a round that
                                  overflows it falls back to full bitset scans (0 = auto)  */

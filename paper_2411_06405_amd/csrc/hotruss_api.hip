@@ -199,17 +199,29 @@ hoStatus run_init(const Dev& d, uint32_t* out_sup, const hoTuning* tune, hipStre
   const size_t lds = (size_t)d.W * 8;
   const unsigned rows_grid = grid_for(d.n, 1, 64);
   hipLaunchKernelGGL(k_build_L1, dim3(rows_grid), dim3(T), lds, s, d);
-  if (d.h >= 2) hipLaunchKernelGGL(k_build_L2, dim3(rows_grid), dim3(T), lds, s, d);
+  const uint32_t dthr = tune && tune->dense_threshold ? tune->dense_threshold : 32;
+  if (d.h >= 2) hipLaunchKernelGGL(k_build_L2, dim3(rows_grid), dim3(T), lds, s, d, dthr);
   for (uint32_t j = 3; j <= d.h; ++j)
     hipLaunchKernelGGL(k_build_Lj, dim3(rows_grid), dim3(T), 0, s, d, j);
   uint32_t epw = tune && tune->edges_per_wave ? tune->edges_per_wave : 0;
   if (!epw) epw = d.W <= 8 ? 16 : d.W <= 32 ? 4 : 1;
   if (sup0) HIPCHK(hipEventRecord(sup0, s));
-  if (epw >= 16) hipLaunchKernelGGL(k_support_init<4>, dim3(grid_for(d.m, T / 4)), dim3(T), 0, s, d, out_sup);
-  else if (epw >= 8) hipLaunchKernelGGL(k_support_init<8>, dim3(grid_for(d.m, T / 8)), dim3(T), 0, s, d, out_sup);
-  else if (epw >= 4) hipLaunchKernelGGL(k_support_init<16>, dim3(grid_for(d.m, T / 16)), dim3(T), 0, s, d, out_sup);
-  else if (epw >= 2) hipLaunchKernelGGL(k_support_init<32>, dim3(grid_for(d.m, T / 32)), dim3(T), 0, s, d, out_sup);
-  else hipLaunchKernelGGL(k_support_init<64>, dim3(grid_for(d.m, T / 64)), dim3(T), 0, s, d, out_sup);
+  const bool wide = tune && tune->word_bits == 128;
+#define HO_SUPINIT(G)                                                                       \
+  do {                                                                                      \
+    if (wide)                                                                               \
+      hipLaunchKernelGGL((k_support_init<G, 2>), dim3(grid_for(d.m, T / G)), dim3(T), 0, s, \
+                         d, out_sup);                                                       \
+    else                                                                                    \
+      hipLaunchKernelGGL((k_support_init<G, 1>), dim3(grid_for(d.m, T / G)), dim3(T), 0, s, \
+                         d, out_sup);                                                       \
+  } while (0)
+  if (epw >= 16) HO_SUPINIT(4);
+  else if (epw >= 8) HO_SUPINIT(8);
+  else if (epw >= 4) HO_SUPINIT(16);
+  else if (epw >= 2) HO_SUPINIT(32);
+  else HO_SUPINIT(64);
+#undef HO_SUPINIT
   if (sup1) HIPCHK(hipEventRecord(sup1, s));
   HIPCHK(hipGetLastError());
   return HO_OK;
@@ -231,8 +243,11 @@ RoundGrid plain_grid(uint64_t m, const hoTuning* tune) {
 }
 
 RoundGrid batch_grid(uint32_t slots, const hoTuning* tune) {
-  // about 8 workgroups per CU across all slots, at least 4 per slot
-  const unsigned total = tune && tune->grid_blocks ? tune->grid_blocks : (unsigned)num_cu() * 8;
+  // Up to 256 workgroups per slot (64 per CU across all slots): a slot in a
+  // large round gets a wide grid while the workgroups of slots with little or
+  // no work in this step return at once.  Narrower per-slot grids make every
+  // step wait on the slot with the largest round.
+  const unsigned total = tune && tune->grid_blocks ? tune->grid_blocks : (unsigned)num_cu() * 64;
   const unsigned per = std::max(4u, std::min(256u, total / std::max(1u, slots)));
   RoundGrid g{std::min<unsigned>(MIN_PART, per), per, per, per};
   return g;

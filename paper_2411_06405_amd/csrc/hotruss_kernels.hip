@@ -188,23 +188,47 @@ __global__ void __launch_bounds__(256) k_build_L1(Dev d) {
   }
 }
 
-// Level 2 by top-down expansion: scatter the adjacency of every z in N[x]
-// into an LDS row.
-__global__ void __launch_bounds__(256) k_build_L2(Dev d) {
+// Level 2.  Each row is built in LDS, by whichever of two frontier
+// expansions reads less: top-down (sparse) scatters the adjacency of every
+// z in N[x]; bottom-up (dense) ORs the level-1 rows of every z in N[x]
+// (B(x,2) = union of N[z] over z in N[x]).  The dense form is taken when the
+// frontier's adjacency entries exceed dthr/16 times the bitset words it
+// would read, (deg(x)+1)·W.
+__global__ void __launch_bounds__(256) k_build_L2(Dev d, uint32_t dthr) {
   extern __shared__ uint64_t srow[];
+  __shared__ uint32_t s_fsum;
   if (d.ctl->err) return;
   const uint32_t lane = lane_id(), wv = threadIdx.x / WAVE, nw = blockDim.x / WAVE;
+  const uint64_t* L1 = d.L[1];
   for (uint32_t x = blockIdx.x; x < d.n; x += gridDim.x) {
+    const uint32_t beg = d.rp[x], end = d.rp[x + 1];
+    if (threadIdx.x == 0) s_fsum = 0;
     for (uint32_t i = threadIdx.x; i < d.W; i += blockDim.x) srow[i] = 0;
     __syncthreads();
-    const uint32_t beg = d.rp[x], end = d.rp[x + 1];
-    // z = x (index beg-1) and every neighbour z = ci[q]
-    for (uint32_t q = beg + wv; q < end + 1; q += nw) {
-      const uint32_t z = (q == end) ? x : d.ci[q];
-      if (lane == 0) atomicOr(&srow[z >> 6], 1ull << (z & 63));
-      for (uint32_t j = d.rp[z] + lane; j < d.rp[z + 1]; j += WAVE) {
-        const uint32_t y = d.ci[j];
-        atomicOr(&srow[y >> 6], 1ull << (y & 63));
+    uint32_t fs = 0;
+    for (uint32_t q = beg + threadIdx.x; q < end; q += blockDim.x) {
+      const uint32_t z = d.ci[q];
+      fs += d.rp[z + 1] - d.rp[z];
+    }
+    fs = wave_sum(fs);
+    if (lane == 0 && fs) atomicAdd(&s_fsum, fs);
+    __syncthreads();
+    const bool dense = (uint64_t)s_fsum * 16 > (uint64_t)dthr * (end - beg + 1) * d.W;
+    if (dense) {
+      for (uint32_t i = threadIdx.x; i < d.W; i += blockDim.x) {
+        uint64_t acc = L1[(size_t)x * d.W + i];
+        for (uint32_t q = beg; q < end; ++q) acc |= L1[(size_t)d.ci[q] * d.W + i];
+        srow[i] = acc;
+      }
+    } else {
+      // z = x (index end) and every neighbour z = ci[q]
+      for (uint32_t q = beg + wv; q < end + 1; q += nw) {
+        const uint32_t z = (q == end) ? x : d.ci[q];
+        if (lane == 0) atomicOr(&srow[z >> 6], 1ull << (z & 63));
+        for (uint32_t k = d.rp[z] + lane; k < d.rp[z + 1]; k += WAVE) {
+          const uint32_t y = d.ci[k];
+          atomicOr(&srow[y >> 6], 1ull << (y & 63));
+        }
       }
     }
     __syncthreads();
@@ -231,18 +255,29 @@ __global__ void __launch_bounds__(256) k_build_Lj(Dev d, uint32_t j) {
 }
 
 // Initial h-support of every edge: |L[h](u) & L[h](v)| - 2 (Def. 3).
-// G lanes cooperate on one edge.
-template <int G>
+// G lanes cooperate on one edge; each lane loads V 64-bit words at a time
+// (V = 1: 64-bit loads, V = 2: 128-bit loads; rows are 64-byte aligned).
+template <int G, int V>
 __global__ void __launch_bounds__(256) k_support_init(Dev d, uint32_t* __restrict__ out) {
   if (d.ctl->err) return;
   const uint64_t* Lh = d.L[d.h];
   const uint32_t sub = threadIdx.x & (G - 1);
   const uint32_t gpb = blockDim.x / G;
+  const uint32_t nv = d.W / V;  // W is a multiple of 8
   for (uint32_t e = blockIdx.x * gpb + threadIdx.x / G; e < d.m; e += gridDim.x * gpb) {
     const uint64_t* a = Lh + (size_t)d.eu[e] * d.W;
     const uint64_t* b = Lh + (size_t)d.ev[e] * d.W;
     uint32_t c = 0;
-    for (uint32_t i = sub; i < d.W; i += G) c += __popcll(a[i] & b[i]);
+    if constexpr (V == 2) {
+      const ulonglong2* a2 = reinterpret_cast<const ulonglong2*>(a);
+      const ulonglong2* b2 = reinterpret_cast<const ulonglong2*>(b);
+      for (uint32_t i = sub; i < nv; i += G) {
+        const ulonglong2 x = a2[i], y = b2[i];
+        c += __popcll(x.x & y.x) + __popcll(x.y & y.y);
+      }
+    } else {
+      for (uint32_t i = sub; i < nv; i += G) c += __popcll(a[i] & b[i]);
+    }
     for (int o = G / 2; o > 0; o >>= 1) c += __shfl_xor(c, o, WAVE);
     if (sub == 0) out[e] = c - 2;
   }

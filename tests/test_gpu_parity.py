@@ -23,12 +23,17 @@ def test_d1_exact(seed, h):
     assert_exact(W.d1(seed), h)
 
 
+@pytest.mark.parametrize("tune", [None, {"dense_threshold": 1}, {"dense_threshold": 1 << 30},
+                                  {"word_bits": 128, "edges_per_wave": 16},
+                                  {"word_bits": 128, "edges_per_wave": 1}])
 @pytest.mark.parametrize("h", [1, 2, 3])
-def test_support_exact(h):
+def test_support_exact(h, tune):
+    # every initial-pass setting (bottom-up / top-down level-2 build, load
+    # width, edges per wavefront) gives the oracle's h-support
     import paper_2411_06405_amd as ht
     for g in (W.d1(0), W.d2(n=3000), W.d3(scale=10)):
-        s = ht.h_support_graph(g, h)
-        assert np.array_equal(s, oracle.h_support(g, h)), (g.name, h)
+        s = ht.h_support_graph(g, h, tune=tune)
+        assert np.array_equal(s, oracle.h_support(g, h)), (g.name, h, tune)
 
 
 @pytest.mark.parametrize("make", [
