@@ -296,23 +296,17 @@ struct RoundCtx {
 __device__ __forceinline__ RoundCtx round_ctx(const Ctl* c) { return RoundCtx{c->r, c->k, c->r & 1}; }
 
 // ---- work item emission (all 64 lanes call; per-lane counts may be 0) ----
-// Items over the CSR row of z: nv = deg(z) + extra virtual entries, CHUNK per
-// item; virtual index 0 is the extra candidate when extra = 1.
-__device__ void emit_row_items(const Dev& d, uint32_t list, bool active, uint32_t kind,
-                               uint32_t x, uint32_t y, uint32_t z, uint32_t extra) {
-  uint32_t nch = 0, base = 0, nv = 0;
-  if (active) {
-    base = d.rp[z];
-    nv = d.rp[z + 1] - base + extra;
-    nch = (nv + CHUNK - 1) / CHUNK;
-  }
-  const uint32_t slot = wave_reserve(&d.ctl->nit[list], nch);
-  Item* L = d.itl[list];
+// Items over a CSR row: nv = deg + extra virtual entries, CHUNK per item;
+// virtual index 0 is the extra candidate when extra = 1.  Writes `nch` items
+// starting at list index idx (reserved by the caller).
+__device__ __forceinline__ void put_row_items(const Dev& d, uint32_t list, uint32_t idx,
+                                              uint32_t nch, uint32_t kind, uint32_t x, uint32_t y,
+                                              uint32_t base, uint32_t nv, uint32_t extra) {
   bool over = false;
   for (uint32_t c = 0; c < nch; ++c) {
-    const uint32_t idx = slot + c;
     const uint32_t vs = c * CHUNK;
-    if (idx < d.itcap) L[idx] = Item{x, y, base, item_meta(kind, extra, min(CHUNK, nv - vs), vs)};
+    if (idx + c < d.itcap)
+      d.itl[list][idx + c] = Item{x, y, base, item_meta(kind, extra, min(CHUNK, nv - vs), vs)};
     else over = true;
   }
   if (over) d.ctl->iovf[list] = 1;
@@ -421,10 +415,23 @@ __device__ void mark_edge(const Dev& d, const RoundCtx& rc, bool valid, uint32_t
   // level 2: a lost neighbour b (candidates (a, y), y in b's old neighbourhood,
   // plus (a, b) itself) and symmetrically; level-1 events (a->b), (b->a):
   // candidates (y, b), y a live neighbour of a, and symmetrically.
-  emit_row_items(d, 2, valid, KIND_A_SLOTS, a, b, b, 1);
-  emit_row_items(d, 2, valid, KIND_A_SLOTS, b, a, a, 1);
-  emit_row_items(d, 2, valid, KIND_B_SLOTS, a, b, a, 0);
-  emit_row_items(d, 2, valid, KIND_B_SLOTS, b, a, b, 0);
+  // (one reservation for the four item groups)
+  uint32_t ba = 0, da = 0, bb = 0, db = 0;
+  if (valid) {
+    ba = d.rp[a];
+    da = d.rp[a + 1] - ba;
+    bb = d.rp[b];
+    db = d.rp[b + 1] - bb;
+  }
+  const uint32_t n0 = valid ? (db + CHUNK) / CHUNK : 0;      // (a, y), y in N(b); + (a, b)
+  const uint32_t n1 = valid ? (da + CHUNK) / CHUNK : 0;      // (b, y), y in N(a); + (b, a)
+  const uint32_t n2 = valid ? (da + CHUNK - 1) / CHUNK : 0;  // (y, b), y in N(a)
+  const uint32_t n3 = valid ? (db + CHUNK - 1) / CHUNK : 0;  // (y, a), y in N(b)
+  const uint32_t slot = wave_reserve(&d.ctl->nit[2], n0 + n1 + n2 + n3);
+  put_row_items(d, 2, slot, n0, KIND_A_SLOTS, a, b, bb, db + 1, 1);
+  put_row_items(d, 2, slot + n0, n1, KIND_A_SLOTS, b, a, ba, da + 1, 1);
+  put_row_items(d, 2, slot + n0 + n1, n2, KIND_B_SLOTS, a, b, ba, da, 0);
+  put_row_items(d, 2, slot + n0 + n1 + n2, n3, KIND_B_SLOTS, b, a, bb, db, 0);
   for (uint32_t j = 3; j <= d.h; ++j) {
     emit_word_items(d, j, valid, a, b);
     emit_word_items(d, j, valid, b, a);
@@ -617,17 +624,23 @@ __global__ void __launch_bounds__(LV_THREADS) k_level(const Dev* __restrict__ de
       }
     }
     // quick filters: a real pair, still in the j-ball, not within j-1 hops
+    // (both balls are symmetric, so both bits are read from the row of the
+    // smaller vertex, together with the two row extents)
     uint32_t a = 0, b = 0, beg = 0, deg = 0;
     if (have) {
-      have = X != Wv && getbit(Lj, d.W, min(X, Wv), max(X, Wv));
+      have = X != Wv;
       if (have) {
-        const uint32_t bx = d.rp[X], dx = d.rp[X + 1] - bx;
-        const uint32_t bw = d.rp[Wv], dw = d.rp[Wv + 1] - bw;
+        const size_t o = (size_t)min(X, Wv) * d.W + (max(X, Wv) >> 6);
+        const uint64_t sh = max(X, Wv) & 63;
+        const uint64_t wj = Lj[o], wp = Lp[o];
+        const uint32_t bx = d.rp[X], ex = d.rp[X + 1];
+        const uint32_t bw = d.rp[Wv], ew = d.rp[Wv + 1];
+        const uint32_t dx = ex - bx, dw = ew - bw;
         a = dx <= dw ? X : Wv;
         b = dx <= dw ? Wv : X;
         beg = dx <= dw ? bx : bw;
         deg = dx <= dw ? dx : dw;
-        have = !getbit(Lp, d.W, a, b);
+        have = ((wj >> sh) & 1ull) && !((wp >> sh) & 1ull);
       }
     }
     const uint64_t bal = __ballot(have);
@@ -688,12 +701,40 @@ __global__ void __launch_bounds__(LV_THREADS) k_level(const Dev* __restrict__ de
       if (counting && (w1 || w2)) atomicAdd(&s_stat[4], (uint32_t)w1 + (uint32_t)w2);
       const uint64_t exw = ((uint64_t)x << 32) | w, ewx = ((uint64_t)w << 32) | x;
       record_events(d, j, rc.p, (uint32_t)w1 + (uint32_t)w2, w1 ? exw : ewx, ewx);
-      if (j == d.h) {
-        emit_support_items(d, w1, x, w);
-        emit_support_items(d, w2, w, x);
-      } else {
-        emit_row_items(d, j + 1, w1, KIND_B_SLOTS, x, w, x, 1);
-        emit_row_items(d, j + 1, w2, KIND_B_SLOTS, w, x, w, 1);
+      // follow-up items of both events with one reservation: the support
+      // update over the row of the event's source (j == h), else the next
+      // level's candidates (y, w) over that row plus (x, w) itself
+      {
+        const uint32_t extra = j == d.h ? 0u : 1u;
+        const uint32_t list = j == d.h ? d.h + 1 : j + 1;
+        const uint32_t kind = j == d.h ? 0u : KIND_B_SLOTS;
+        uint32_t bx = 0, nx = 0, bw = 0, nw = 0;
+        if (w1) {
+          bx = d.rp[x];
+          nx = d.rp[x + 1] - bx + extra;
+        }
+        if (w2) {
+          bw = d.rp[w];
+          nw = d.rp[w + 1] - bw + extra;
+        }
+        const uint32_t c1 = (nx + CHUNK - 1) / CHUNK, c2 = (nw + CHUNK - 1) / CHUNK;
+        const uint32_t slot = wave_reserve(&d.ctl->nit[list], c1 + c2);
+        if (j == d.h) {
+          // support items carry the slot base of their chunk
+          for (uint32_t c = 0; c < c1; ++c) {
+            if (slot + c < d.itcap)
+              d.itl[list][slot + c] = Item{x, w, bx + c * CHUNK, item_meta(0, 0, min(CHUNK, nx - c * CHUNK), 0)};
+            else d.ctl->iovf[list] = 1;
+          }
+          for (uint32_t c = 0; c < c2; ++c) {
+            if (slot + c1 + c < d.itcap)
+              d.itl[list][slot + c1 + c] = Item{w, x, bw + c * CHUNK, item_meta(0, 0, min(CHUNK, nw - c * CHUNK), 0)};
+            else d.ctl->iovf[list] = 1;
+          }
+        } else {
+          put_row_items(d, list, slot, c1, kind, x, w, bx, nx, extra);
+          put_row_items(d, list, slot + c1, c2, kind, w, x, bw, nw, extra);
+        }
       }
     }
     __syncthreads();
