@@ -5,8 +5,10 @@ library is checked against.  Only the test suite, the smoke check and the
 benchmark's CPU-baseline leg may import it.  It shares no code with the GPU
 library (``paper_2411_06405_amd``) and never imports it.
 """
-from .oracle import (OracleError, build, certify, decompose, h_support, lib_path)
+from .oracle import (OracleError, build, certify, decompose, h_support, h_support_edges,
+                     lib_path)
 from .brute import brute_trussness, brute_h_support
 
-__all__ = ["OracleError", "build", "certify", "decompose", "h_support", "lib_path",
+__all__ = ["OracleError", "build", "certify", "decompose", "h_support", "h_support_edges",
+           "lib_path",
            "brute_trussness", "brute_h_support"]

@@ -225,6 +225,44 @@ int oracle_h_support(uint32_t n, const uint32_t *row_ptr, const uint32_t *col_id
     return err ? OR_ERR_MEM : OR_OK;
 }
 
+/* sup_S(e,h) for the listed edges only (same evaluation as above), for
+ * graphs too large to evaluate every edge: sup_out[i] = sup_S(edges[i],h). */
+int oracle_h_support_edges(uint32_t n, const uint32_t *row_ptr, const uint32_t *col_idx,
+                           uint32_t h, const uint32_t *key, uint32_t thr,
+                           const uint32_t *edges, uint64_t num_edges,
+                           uint32_t *sup_out, int threads)
+{
+    if (!row_ptr || !col_idx || !edges || !sup_out || h == 0) return OR_ERR_ARG;
+    og_t g;
+    int rc = og_build(&g, n, row_ptr, col_idx);
+    if (rc) { og_free(&g); return rc; }
+    filt_t f = { key, thr };
+    int nt = nthreads_or_default(threads);
+    int err = 0;
+#pragma omp parallel num_threads(nt)
+    {
+        bfs_ws w; uint32_t mk = 0;
+        if (ws_init(&w, n)) {
+#pragma omp atomic write
+            err = 1;
+        } else {
+#pragma omp for schedule(dynamic, 4)
+            for (int64_t i = 0; i < (int64_t)num_edges; ++i) {
+                uint32_t e = edges[i];
+                if (e >= g.m) {
+#pragma omp atomic write
+                    err = 2;
+                    continue;
+                }
+                sup_out[i] = in_S(&f, e) ? (uint32_t)h_support(&g, &f, e, h, &w, &mk) : 0u;
+            }
+        }
+        ws_free(&w);
+    }
+    og_free(&g);
+    return err == 1 ? OR_ERR_MEM : (err == 2 ? OR_ERR_ARG : OR_OK);
+}
+
 /* Peeling decomposition (Algorithm 1, bulk-synchronous rounds).
  *
  * t_out[m]   h-trussness of every edge (always >= 2);

@@ -42,11 +42,14 @@ def _bind(path):
     u64p = C.POINTER(C.c_uint64)
     lib.oracle_h_support.argtypes = [C.c_uint32, u32p, u32p, C.c_uint32, u32p,
                                      C.c_uint32, u32p, C.c_int]
+    lib.oracle_h_support_edges.argtypes = [C.c_uint32, u32p, u32p, C.c_uint32, u32p,
+                                           C.c_uint32, u32p, C.c_uint64, u32p, C.c_int]
     lib.oracle_decompose.argtypes = [C.c_uint32, u32p, u32p, C.c_uint32, u32p, u32p,
                                      u32p, u32p, C.c_uint64, u64p, C.c_int]
     lib.oracle_certify.argtypes = [C.c_uint32, u32p, u32p, C.c_uint32, u32p, u32p,
                                    u32p, C.c_uint64, u64p, C.c_int]
-    for f in (lib.oracle_h_support, lib.oracle_decompose, lib.oracle_certify):
+    for f in (lib.oracle_h_support, lib.oracle_h_support_edges, lib.oracle_decompose,
+              lib.oracle_certify):
         f.restype = C.c_int
     return lib
 
@@ -95,6 +98,23 @@ def h_support(g, h: int, key=None, thr: int = 0, threads: int = 0, lib=None) -> 
     if rc != OR_OK:
         raise OracleError(f"oracle_h_support failed: {rc}")
     return out
+
+def h_support_edges(g, h: int, edges, key=None, thr: int = 0, threads: int = 0,
+                    lib=None) -> np.ndarray:
+    """sup_S(e,h) for the listed canonical edges only (S as in h_support)."""
+    lib = _load(lib)
+    rp, rpp, ci, cip = _csr(g)
+    edges, ep = _u32(edges)
+    out = np.zeros(edges.size, dtype=np.uint32)
+    kp = None
+    if key is not None:
+        key, kp = _u32(key)
+    rc = lib.oracle_h_support_edges(g.n, rpp, cip, int(h), kp, int(thr), ep, edges.size,
+                                    out.ctypes.data_as(C.POINTER(C.c_uint32)), int(threads))
+    if rc != OR_OK:
+        raise OracleError(f"oracle_h_support_edges failed: {rc}")
+    return out
+
 
 def decompose(g, h: int, threads: int = 0, round_cap: int = 1 << 20, lib=None):
     """Return (t, rho, info) with info = {rounds, levels, evals, round_k, round_size}."""

@@ -1,0 +1,46 @@
+"""The autotuner on the GPU: the setting it picks is cached and gives results
+identical to the oracle (knobs change speed, never results)."""
+import numpy as np
+import pytest
+
+import oracle
+from graphgen import workloads as W
+from tests.gpu_helpers import run_gpu
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+
+
+@pytest.mark.parametrize("h", [2, 3])
+def test_autotuned_setting_is_exact_and_cached(tmp_path, h):
+    from paper_2411_06405_amd import autotune as A
+    g = W.d2(n=3000) if h == 2 else W.d2(n=1200)
+    cache = tmp_path / "tune.json"
+    tune = A.autotune(g.row_ptr, g.col_idx, g.n, h, device="cuda:0", cache=cache, repeats=1)
+    assert set(tune) == {"word_bits", "edges_per_wave", "dense_threshold"}
+    assert A.Cache(cache).data, "measurement not cached"
+    again = A.autotune(g.row_ptr, g.col_idx, g.n, h, device="cuda:0", cache=cache)
+    assert again == tune
+    t, rho = run_gpu(g, h, tune=tune)
+    to, ro, _ = oracle.decompose(g, h)
+    assert np.array_equal(t, to) and np.array_equal(rho, ro)
+
+
+def test_autotune_batch_is_exact(tmp_path):
+    import paper_2411_06405_amd as ht
+    from graphgen import concat
+    from paper_2411_06405_amd import autotune as A
+    specs = [(1200, 3, 2, 5), (1500, 4, 3, 6), (1000, 5, 2, 7)]
+    gs = [W.d4_graph(s) for s in specs]
+    hs = np.array([s[2] for s in specs], dtype=np.uint32)
+    tune = A.autotune_batch(gs, hs, device="cuda:0", cache=tmp_path / "t.json", sample=2)
+    ts, rs = ht.decompose_batch(concat(gs, hs), tune=tune, device="cuda:0")
+    for g, h, t, r in zip(gs, hs, ts, rs):
+        to, ro, _ = oracle.decompose(g, int(h))
+        assert np.array_equal(t, to) and np.array_equal(r, ro)

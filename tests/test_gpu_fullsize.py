@@ -1,0 +1,64 @@
+"""Parity at the full benchmark sizes, in the launch configuration bench.py
+times (graph-driven rounds, default tuning, workspace reused): the oracle
+cannot decompose these graphs in test time, so the GPU's (t, rho) is checked
+with the oracle's exactness certificate -- every edge for the round/level
+structure (C0), a sample of edges for the two support conditions (C1, C2) --
+and against properties that hold at any size."""
+import numpy as np
+import pytest
+
+from graphgen import workloads as W
+from tests.gpu_helpers import assert_certified
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+
+
+def _decompose_like_bench(g, h):
+    import torch
+    import paper_2411_06405_amd as ht
+    dev = torch.device("cuda:0")
+    rp = torch.from_numpy(g.row_ptr.view(np.int32)).to(dev)
+    ci = torch.from_numpy(g.col_idx.view(np.int32)).to(dev)
+    ws = ht.alloc_workspace(g.n, g.m, h, device=dev)
+    print(f"[gpu] {g.name} n={g.n} m={g.m} h={h} (bench configuration)", flush=True)
+    t, rho = ht.decompose(rp, ci, g.n, h, workspace=ws, device=dev)
+    st = ht.last_stats()
+    sup = ht.h_support(rp, ci, g.n, h, workspace=ws, device=dev)
+    out = (ht.to_numpy_u32(t), ht.to_numpy_u32(rho), ht.to_numpy_u32(sup), st)
+    del ws
+    torch.cuda.empty_cache()
+    return out
+
+
+@pytest.mark.parametrize("make,h,nsample", [
+    (lambda: W.d2(), 2, 3000),          # Chung-Lu n = 100,000 (the bench workload)
+    (lambda: W.d3(), 2, 400),           # R-MAT scale 18
+])
+def test_fullsize_certified(make, h, nsample):
+    g = make()
+    t, rho, sup, st = _decompose_like_bench(g, h)
+    # properties at any size: 2 <= t <= sup_G + 2; rounds numbered 0..R-1
+    assert t.min() >= 2 and np.all(t <= sup.astype(np.int64) + 2)
+    assert int(rho.max()) + 1 == st["rounds"]
+    assert np.unique(rho).size == st["rounds"]
+    n = assert_certified(g, h, t, rho, nsample)
+    print(f"[gpu] certified {n} sampled edges, {st['rounds']} rounds", flush=True)
+
+
+def test_fullsize_initial_support_sampled():
+    # the initial h-support of sampled edges of the full Chung-Lu graph
+    # against the oracle's BFS, edge by edge
+    import oracle
+    g = W.d2()
+    _, _, sup, _ = _decompose_like_bench(g, 2)
+    rng = np.random.default_rng(1)
+    sample = rng.choice(g.m, 500, replace=False)
+    ref = oracle.h_support_edges(g, 2, sample.astype(np.uint32))
+    assert np.array_equal(sup[sample], ref)

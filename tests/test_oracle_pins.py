@@ -141,3 +141,13 @@ def test_h_support_subgraph_filter(oracle_mod):
         bu = set(nx.single_source_shortest_path_length(G, u, cutoff=2)) - {u}
         bv = set(nx.single_source_shortest_path_length(G, v, cutoff=2)) - {v}
         assert sup[i] == len(bu & bv)
+
+
+def test_sampled_support_matches_full(oracle_mod):
+    # entry-point consistency (not a pin): the sampled evaluation used at full
+    # benchmark sizes returns the full evaluation's values on its edges
+    g = W.d2(n=2000)
+    for h in (1, 2, 3):
+        full = oracle_mod.h_support(g, h)
+        e = np.random.default_rng(h).choice(g.m, 50, replace=False).astype(np.uint32)
+        assert np.array_equal(oracle_mod.h_support_edges(g, h, e), full[e])
