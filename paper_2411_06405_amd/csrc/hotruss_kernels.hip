@@ -538,6 +538,9 @@ __global__ void __launch_bounds__(LV_THREADS) k_level(const Dev* __restrict__ de
   Ctl* c = d.ctl;
   if (c->done) return;
   if (c->halt) return;
+  // a round that peels every remaining edge leaves no ball or support that
+  // could matter: the decomposition ends with it
+  if (c->nR == c->live) return;
   if (c->iovf[j] || (d.serial & 4u)) {
     // work list overflowed: leave this level to the serial kernel the host runs
     if (blockIdx.x == 0 && threadIdx.x == 0) {
@@ -759,6 +762,7 @@ __global__ void __launch_bounds__(256) k_support(const Dev* __restrict__ devs) {
   if (c->done) return;
   const uint32_t list = d.h + 1;
   if (c->halt) return;
+  if (c->nR == c->live) return;  // the last round: nothing left to update
   if (c->iovf[list] || (d.serial & 8u)) {
     if (blockIdx.x == 0 && threadIdx.x == 0) {
       c->halt = 1;
