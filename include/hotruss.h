@@ -85,6 +85,7 @@ typedef struct {
 #define HO_FLAG_STATS 0x2u      /* time every kernel with HIP events (implies host loop) */
 #define HO_FLAG_SERIAL_LEVELS 0x4u   /* testing: always take the serial ball-change path */
 #define HO_FLAG_SERIAL_SUPPORT 0x8u  /* testing: always take the serial support path     */
+#define HO_FLAG_COMPACT_EACH 0x10u   /* testing: compact the adjacency rows at every chance  */
 
 /* Work counters of the last decomposition on this host thread. */
 typedef struct {

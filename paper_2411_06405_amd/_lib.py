@@ -23,6 +23,7 @@ HO_FLAG_HOST_LOOP = 0x1
 HO_FLAG_STATS = 0x2
 HO_FLAG_SERIAL_LEVELS = 0x4
 HO_FLAG_SERIAL_SUPPORT = 0x8
+HO_FLAG_COMPACT_EACH = 0x10
 
 
 class HotrussError(RuntimeError):

@@ -19,6 +19,9 @@ __global__ void k_level_serial(const Dev* __restrict__ dp, uint32_t j);
 __global__ void k_support_serial(const Dev* __restrict__ dp);
 }  // namespace hotruss
 
+// status words per engine slot: {done, halt, live edges, unused}
+#define HO_STATUS_WORDS 4
+
 namespace hotruss {
 
 namespace {
@@ -33,7 +36,8 @@ struct Plan {
   bool full = true;  // decomposition (false: support only)
   size_t off_ctl, off_eid, off_eu, off_ev, off_s1, off_s2, off_srem, off_upcnt, off_upoff,
       off_scan, off_minpart, off_sup, off_rho, off_R0, off_R1, off_L[HMAX + 1],
-      off_Dm[HMAX + 1], off_evl[HMAX + 1][2], off_itl[HMAX + 2];
+      off_Dm[HMAX + 1], off_evl[HMAX + 1][2], off_itl[HMAX + 2], off_cix, off_len, off_tci,
+      off_teid;
   size_t total = 0;
 };
 
@@ -78,6 +82,10 @@ bool make_plan(uint32_t n, uint64_t m, uint32_t h, const hoTuning* tune, bool fu
   p.off_minpart = take(4 * MIN_PART);
   p.off_sup = take(4 * m + 4);
   p.off_rho = take(full ? 4 * m + 4 : 0);
+  p.off_cix = take(full ? 8 * m + 4 : 0);
+  p.off_len = take(full ? 4 * (size_t)n + 4 : 0);
+  p.off_tci = take(full ? 8 * m + 4 : 0);
+  p.off_teid = take(full ? 8 * m + 4 : 0);
   p.off_R0 = take(full ? 4 * m + 4 : 0);
   p.off_R1 = take(full ? 4 * m + 4 : 0);
   for (uint32_t j = 0; j <= HMAX; ++j) {
@@ -156,6 +164,10 @@ Dev carve(const Plan& p, void* ws, const uint32_t* rp, const uint32_t* ci, uint3
   if (p.full) {
     d.R[0] = (uint32_t*)at(p.off_R0);
     d.R[1] = (uint32_t*)at(p.off_R1);
+    d.cix = (uint32_t*)at(p.off_cix);
+    d.len = (uint32_t*)at(p.off_len);
+    d.tci = (uint32_t*)at(p.off_tci);
+    d.teid = (uint32_t*)at(p.off_teid);
   }
   for (uint32_t j = 1; j <= p.h; ++j) {
     d.L[j] = (uint64_t*)at(p.off_L[j]);
@@ -266,6 +278,13 @@ void launch_step(const Dev* devs, uint32_t S, uint32_t hmax, const RoundGrid& g,
   hipLaunchKernelGGL(k_advance, dim3(1, S), dim3(64), 0, s, devs);
 }
 
+void launch_compact(const Dev& d, hipStream_t s) {
+  const unsigned T = 256;
+  const unsigned g = grid_for(d.n, T / WAVE);
+  hipLaunchKernelGGL(k_compact_rows, dim3(g), dim3(T), 0, s, d);
+  hipLaunchKernelGGL(k_compact_commit, dim3(g), dim3(T), 0, s, d);
+}
+
 hoStatus read_ctl(const Dev& d, Ctl* host, hipStream_t s) {
   HIPCHK(hipMemcpyAsync(host, d.ctl, sizeof(Ctl), hipMemcpyDeviceToHost, s));
   HIPCHK(hipStreamSynchronize(s));
@@ -318,7 +337,7 @@ hoStatus steps_host(const Dev& d, const RoundGrid& g, hipStream_t s, uint32_t fr
     }
     if (serial) {
       HIPCHK(hipMemsetAsync(&d.ctl->halt, 0, sizeof(uint32_t), s));
-      HIPCHK(hipMemsetAsync(&d.status[1], 0, sizeof(uint32_t), s));
+      HIPCHK(hipMemsetAsync(&d.status[1], 0, sizeof(uint32_t), s));  // host-driven, not captured
       HOCHK(tm.begin(s));
       if (step <= d.h) hipLaunchKernelGGL(k_level_serial, dim3(g.level), dim3(T), 0, s, dp, step);
       else hipLaunchKernelGGL(k_support_serial, dim3(g.support), dim3(T), 0, s, dp);
@@ -423,7 +442,8 @@ std::vector<GraphCacheEntry> g_graph_cache;
 // counters and the control block of an idle slot (finished, so every round
 // kernel returns at once).
 size_t engine_header_bytes(uint32_t S) {
-  return up(sizeof(Dev) * S) + up(8ull * S) + up(4ull * NSTAT * STAT_GRID) + up(sizeof(Ctl));
+  return up(sizeof(Dev) * S) + up(4ull * HO_STATUS_WORDS * S) + up(4ull * NSTAT * STAT_GRID) +
+         up(sizeof(Ctl));
 }
 
 class Engine {
@@ -441,11 +461,14 @@ class Engine {
   std::vector<int> slot_req;
   std::vector<Dev> slot_dev;
   std::vector<uint64_t> slot_since;  // first graph launch that can report on the slot
+  std::vector<uint32_t> live_seen;   // live edges in the slot's latest status snapshot
+  std::vector<uint32_t> compact_at;  // compact the slot's rows once live falls to this
+  std::vector<uint8_t> compact_each; // testing: compact at every opportunity
   Pool pool;
   std::vector<Request> reqs;
   std::vector<size_t> queue;
   Ctl* idle_ctl_d = nullptr;
-  uint32_t* hstat = nullptr;  // pinned: 2 buffers x S x {done, halt}
+  uint32_t* hstat = nullptr;  // pinned: 2 buffers x S x status words, then a Ctl
   Dev* idle_h = nullptr;      // pinned: descriptor of each idle slot
   Dev* dev_h = nullptr;       // pinned: staging of each admitted slot's descriptor
   hipEvent_t ev[2] = {nullptr, nullptr};
@@ -478,31 +501,36 @@ class Engine {
     plain = plain_;
     devs_d = (Dev*)base;
     status_d = (uint32_t*)(base + up(sizeof(Dev) * S));
-    spart_d = (uint32_t*)(base + up(sizeof(Dev) * S) + up(8ull * S));
-    idle_ctl_d = (Ctl*)(base + up(sizeof(Dev) * S) + up(8ull * S) + up(4ull * NSTAT * STAT_GRID));
+    spart_d = (uint32_t*)(base + up(sizeof(Dev) * S) + up(4ull * HO_STATUS_WORDS * S));
+    idle_ctl_d = (Ctl*)(base + up(sizeof(Dev) * S) + up(4ull * HO_STATUS_WORDS * S) +
+                        up(4ull * NSTAT * STAT_GRID));
     pool.reset(engine_header_bytes(S), bytes);
     slot_req.assign(S, -1);
     slot_dev.assign(S, Dev{});
     slot_since.assign(S, 0);
-    HIPCHK(hipHostMalloc((void**)&hstat, 16ull * S + sizeof(Ctl), hipHostMallocDefault));
+    live_seen.assign(S, 0);
+    compact_at.assign(S, 0);
+    compact_each.assign(S, 0);
+    HIPCHK(hipHostMalloc((void**)&hstat, 8ull * HO_STATUS_WORDS * S + sizeof(Ctl),
+                         hipHostMallocDefault));
     HIPCHK(hipHostMalloc((void**)&idle_h, sizeof(Dev) * S, hipHostMallocDefault));
     HIPCHK(hipHostMalloc((void**)&dev_h, sizeof(Dev) * S, hipHostMallocDefault));
     HIPCHK(hipEventCreateWithFlags(&ev[0], hipEventDisableTiming));
     HIPCHK(hipEventCreateWithFlags(&ev[1], hipEventDisableTiming));
     // every slot starts idle: finished status, a descriptor with no levels
     // whose control block says finished, so every round kernel returns at once
-    for (uint32_t i = 0; i < 2 * S; ++i) hstat[i] = (i % 2 == 0) ? 1u : 0u;
-    Ctl* hc = (Ctl*)(hstat + 4ull * S);
+    for (uint32_t i = 0; i < HO_STATUS_WORDS * S; ++i) hstat[i] = (i % HO_STATUS_WORDS == 0) ? 1u : 0u;
+    Ctl* hc = (Ctl*)(hstat + 2ull * HO_STATUS_WORDS * S);
     memset(hc, 0, sizeof(Ctl));
     hc->done = 1;
     for (uint32_t i = 0; i < S; ++i) {
       memset(&idle_h[i], 0, sizeof(Dev));
       idle_h[i].ctl = idle_ctl_d;
-      idle_h[i].status = status_d + 2 * i;
+      idle_h[i].status = status_d + HO_STATUS_WORDS * i;
       idle_h[i].self = devs_d + i;
     }
     HIPCHK(hipMemcpyAsync(idle_ctl_d, hc, sizeof(Ctl), hipMemcpyHostToDevice, s));
-    HIPCHK(hipMemcpyAsync(status_d, hstat, 8ull * S, hipMemcpyHostToDevice, s));
+    HIPCHK(hipMemcpyAsync(status_d, hstat, 4ull * HO_STATUS_WORDS * S, hipMemcpyHostToDevice, s));
     HIPCHK(hipMemcpyAsync(devs_d, idle_h, sizeof(Dev) * S, hipMemcpyHostToDevice, s));
     HIPCHK(hipStreamSynchronize(s));
     return HO_OK;
@@ -544,11 +572,15 @@ class Engine {
       queue.erase(queue.begin() + qi);
       Dev d = carve(r.plan, (void*)(base + off), r.rp, r.ci, r.t, r.rho);
       d.self = devs_d + slot;
-      d.status = status_d + 2 * slot;
+      d.status = status_d + HO_STATUS_WORDS * slot;
       d.nminpart = g.jump;
-      if (r.has_tune) d.serial = r.tune.flags & (HO_FLAG_SERIAL_LEVELS | HO_FLAG_SERIAL_SUPPORT);
+      if (r.has_tune)
+        d.serial = r.tune.flags & (HO_FLAG_SERIAL_LEVELS | HO_FLAG_SERIAL_SUPPORT | HO_FLAG_COMPACT_EACH);
       slot_dev[slot] = d;
       slot_since[slot] = steps;
+      live_seen[slot] = 0;
+      compact_at[slot] = (uint32_t)(r.m / 2);
+      compact_each[slot] = r.has_tune && (r.tune.flags & HO_FLAG_COMPACT_EACH) ? 1 : 0;
       HOCHK(start_slot(d, r.has_tune ? &r.tune : nullptr, sup0, sup1));
     }
     return HO_OK;
@@ -563,6 +595,7 @@ class Engine {
         hipLaunchKernelGGL(k_fill64, dim3(grid_for((size_t)d.n * d.W, T)), dim3(T), 0, s, d.Dm[j],
                            (size_t)d.n * d.W, 0ull);
     HOCHK(run_init(d, d.sup, tune, s, sup0, sup1));
+    hipLaunchKernelGGL(k_init_rows, dim3(grid_for(d.nnz, T)), dim3(T), 0, s, d);
     const size_t i = (size_t)(d.self - devs_d);
     dev_h[i] = d;
     HIPCHK(hipMemcpyAsync(d.self, &dev_h[i], sizeof(Dev), hipMemcpyHostToDevice, s));
@@ -628,11 +661,15 @@ class Engine {
     for (uint32_t i = 0; i < S; ++i) {
       const int ri = slot_req[i];
       if (ri < 0 || at < slot_since[i]) continue;
-      if (st[2 * i + 1]) halted = true;
-      if (!st[2 * i]) continue;
+      const uint32_t* sw = st + HO_STATUS_WORDS * i;
+      if (sw[1]) halted = true;
+      if (!sw[0]) {
+        live_seen[i] = sw[2];
+        continue;
+      }
       Request& r = reqs[ri];
       r.state = 2;
-      r.result = st[2 * i] == 2 ? HO_ERR_BAD_CSR : HO_OK;
+      r.result = sw[0] == 2 ? HO_ERR_BAD_CSR : HO_OK;
       // park the slot before its memory can be handed to another request:
       // replays already in flight still read the old, finished control block
       if (hipMemcpyAsync(devs_d + i, &idle_h[i], sizeof(Dev), hipMemcpyHostToDevice, s) !=
@@ -642,6 +679,22 @@ class Engine {
       slot_req[i] = -1;
     }
     return halted;
+  }
+
+  // Compact the adjacency rows of running slots whose live edge count halved
+  // since the last compaction (enqueued after the launches in flight, so it
+  // runs at a round boundary; the kernels do nothing for a slot that has
+  // finished or halted meanwhile).
+  hoStatus maybe_compact() {
+    for (uint32_t i = 0; i < S; ++i) {
+      if (slot_req[i] < 0 || live_seen[i] == 0) continue;
+      if (!compact_each[i] && live_seen[i] > compact_at[i]) continue;
+      launch_compact(slot_dev[i], s);
+      compact_at[i] = live_seen[i] / 2;
+      live_seen[i] = 0;
+    }
+    HIPCHK(hipGetLastError());
+    return HO_OK;
   }
 
   // Finish the current round of every halted slot from the host.
@@ -673,7 +726,8 @@ class Engine {
         const int buf = (head + inflight) & 1;
         const int which = plain ? (steps == 0 ? 0 : steps < 4 ? 1 : 2) : (queue.empty() ? 2 : 1);
         HIPCHK(hipGraphLaunch(exec[which], s));
-        HIPCHK(hipMemcpyAsync(hstat + 2 * S * buf, status_d, 8ull * S, hipMemcpyDeviceToHost, s));
+        HIPCHK(hipMemcpyAsync(hstat + HO_STATUS_WORDS * S * buf, status_d,
+                              4ull * HO_STATUS_WORDS * S, hipMemcpyDeviceToHost, s));
         HIPCHK(hipEventRecord(ev[buf], s));
         buf_at[buf] = steps++;
         ++launched;
@@ -681,7 +735,7 @@ class Engine {
       }
       if (inflight == 0) break;
       HIPCHK(hipEventSynchronize(ev[head]));
-      const bool halted = retire(hstat + 2 * S * head, buf_at[head]);
+      const bool halted = retire(hstat + HO_STATUS_WORDS * S * head, buf_at[head]);
       if (copy_failed) return HO_ERR_HIP;
       head ^= 1;
       --inflight;
@@ -692,6 +746,7 @@ class Engine {
         HOCHK(recover_halts());
       }
       HOCHK(admit());
+      HOCHK(maybe_compact());
     }
     HIPCHK(hipStreamSynchronize(s));
     return HO_OK;
@@ -714,7 +769,12 @@ hoStatus run_rounds_host(const Dev& d, const RoundGrid& g, hipStream_t s, bool t
   Ctl c;
   hoStatus st = read_ctl(d, &c, s);
   uint64_t rounds = 0;
+  uint32_t compact_at = d.m / 2;
   while (st == HO_OK && !c.done) {
+    if (c.live <= compact_at || (d.serial & HO_FLAG_COMPACT_EACH)) {
+      launch_compact(d, s);
+      compact_at = c.live / 2;
+    }
     if ((st = tm.begin(s)) != HO_OK) break;
     hipLaunchKernelGGL(k_jump_min, dim3(g.jump), dim3(T), 0, s, dp);
     if ((st = tm.end(s, KT_JUMP)) != HO_OK) break;

@@ -76,13 +76,21 @@ struct Dev {
   uint32_t evcap;       // capacity of each level>=2 event list
   uint32_t itcap;       // capacity of each work item list
   uint32_t nminpart;    // blocks of the level-jump minimum kernel
-  uint32_t serial;      // testing: bit 2 forces the serial level path, bit 3 the serial support path
+  uint32_t serial;      // testing: bit 2 forces the serial level path, bit 3 the serial
+                        // support path, bit 4 compacts rows at every chance
   uint32_t* eid;        // slot -> edge id           [2m]
   uint32_t* eu;         // edge id -> lower endpoint  [m]
   uint32_t* ev;         // edge id -> upper endpoint  [m]
   uint32_t* s1;         // edge id -> slot in row eu  [m]
   uint32_t* s2;         // edge id -> slot in row ev  [m]
   uint32_t* srem;       // slot -> round its edge was peeled, ALIVE if in S [2m]
+  // Round kernels read the adjacency through a private copy whose rows are
+  // compacted now and then (live slots first, in order): row x's active
+  // slots are [rp[x], rp[x] + len[x]); slots past len[x] are dead.
+  uint32_t* cix;        // private column ids [2m]
+  uint32_t* len;        // active slots per row [n]
+  uint32_t* tci;        // compaction staging: column ids [2m]
+  uint32_t* teid;       // compaction staging: edge ids [2m]
   uint32_t* up_cnt;     // per row: neighbours above the row vertex [n]
   uint32_t* up_off;     // exclusive prefix sum of up_cnt [n]
   uint32_t* scan_tmp;   // block sums for the scan
@@ -98,11 +106,14 @@ struct Dev {
   Ctl* ctl;
   Dev* self;               // device-resident copy of this struct (round kernels read it)
   uint32_t* spart;         // stats mode: per-workgroup counters [NSTAT][STAT_GRID], else null
-  uint32_t* status;        // this slot's {done, halt} words in the engine's status array
-                           // (done: 1 finished, 2 malformed CSR)
+  uint32_t* status;        // this slot's {done, halt, live, -} words in the engine's status
+                           // array (done: 1 finished, 2 malformed CSR; live: edges left)
 };
 
 __device__ __forceinline__ uint32_t lane_id() { return threadIdx.x & (WAVE - 1); }
+
+// End of row x's active slots (round kernels).
+__device__ __forceinline__ uint32_t row_end(const Dev& d, uint32_t x) { return d.rp[x] + d.len[x]; }
 
 __device__ __forceinline__ uint64_t* row(uint64_t* base, uint32_t W, uint32_t x) {
   return base + (size_t)x * W;

@@ -318,7 +318,7 @@ __device__ void emit_support_items(const Dev& d, bool active, uint32_t a, uint32
   uint32_t nch = 0, base = 0, deg = 0;
   if (active) {
     base = d.rp[a];
-    deg = d.rp[a + 1] - base;
+    deg = row_end(d, a) - base;
     nch = (deg + CHUNK - 1) / CHUNK;
   }
   const uint32_t slot = wave_reserve(&d.ctl->nit[list], nch);
@@ -419,9 +419,9 @@ __device__ void mark_edge(const Dev& d, const RoundCtx& rc, bool valid, uint32_t
   uint32_t ba = 0, da = 0, bb = 0, db = 0;
   if (valid) {
     ba = d.rp[a];
-    da = d.rp[a + 1] - ba;
+    da = row_end(d, a) - ba;
     bb = d.rp[b];
-    db = d.rp[b + 1] - bb;
+    db = row_end(d, b) - bb;
   }
   const uint32_t n0 = valid ? (db + CHUNK) / CHUNK : 0;      // (a, y), y in N(b); + (a, b)
   const uint32_t n1 = valid ? (da + CHUNK) / CHUNK : 0;      // (b, y), y in N(a); + (b, a)
@@ -616,7 +616,7 @@ __global__ void __launch_bounds__(LV_THREADS) k_level(const Dev* __restrict__ de
             const uint32_t sr = d.srem[q];
             if (kind == KIND_A_SLOTS ? sr >= rc.r : sr > rc.r) {
               have = true;
-              const uint32_t y2 = d.ci[q];
+              const uint32_t y2 = d.cix[q];
               X = (kind == KIND_A_SLOTS) ? I.x : y2;
               Wv = (kind == KIND_A_SLOTS) ? y2 : I.y;
             }
@@ -629,17 +629,16 @@ __global__ void __launch_bounds__(LV_THREADS) k_level(const Dev* __restrict__ de
     // quick filters: a real pair, still in the j-ball, not within j-1 hops
     // (both balls are symmetric, so both bits are read from the row of the
     // smaller vertex, together with the two row extents)
-    uint32_t a = 0, b = 0, beg = 0, deg = 0;
+    // the witness probes run over the endpoint with fewer active slots
+    uint32_t b = 0, beg = 0, deg = 0;
     if (have) {
       have = X != Wv;
       if (have) {
         const size_t o = (size_t)min(X, Wv) * d.W + (max(X, Wv) >> 6);
         const uint64_t sh = max(X, Wv) & 63;
         const uint64_t wj = Lj[o], wp = Lp[o];
-        const uint32_t bx = d.rp[X], ex = d.rp[X + 1];
-        const uint32_t bw = d.rp[Wv], ew = d.rp[Wv + 1];
-        const uint32_t dx = ex - bx, dw = ew - bw;
-        a = dx <= dw ? X : Wv;
+        const uint32_t bx = d.rp[X], dx = d.len[X];
+        const uint32_t bw = d.rp[Wv], dw = d.len[Wv];
         b = dx <= dw ? Wv : X;
         beg = dx <= dw ? bx : bw;
         deg = dx <= dw ? dx : dw;
@@ -683,7 +682,7 @@ __global__ void __launch_bounds__(LV_THREADS) k_level(const Dev* __restrict__ de
       }
       if (cflag[lo]) continue;
       const uint32_t q = cbeg[lo] + (pidx - coff[lo]);
-      if (d.srem[q] > rc.r && getbit(Lp, d.W, cb[lo], d.ci[q])) cflag[lo] = 1;
+      if (d.srem[q] > rc.r && getbit(Lp, d.W, cb[lo], d.cix[q])) cflag[lo] = 1;
     }
     __syncthreads();
     // ---- pairs without a witness leave the j-ball (both directions) ----
@@ -714,11 +713,11 @@ __global__ void __launch_bounds__(LV_THREADS) k_level(const Dev* __restrict__ de
         uint32_t bx = 0, nx = 0, bw = 0, nw = 0;
         if (w1) {
           bx = d.rp[x];
-          nx = d.rp[x + 1] - bx + extra;
+          nx = row_end(d, x) - bx + extra;
         }
         if (w2) {
           bw = d.rp[w];
-          nw = d.rp[w + 1] - bw + extra;
+          nw = row_end(d, w) - bw + extra;
         }
         const uint32_t c1 = (nx + CHUNK - 1) / CHUNK, c2 = (nw + CHUNK - 1) / CHUNK;
         const uint32_t slot = wave_reserve(&d.ctl->nit[list], c1 + c2);
@@ -791,7 +790,7 @@ __global__ void __launch_bounds__(256) k_support(const Dev* __restrict__ devs) {
     if (lane < len) {
       const uint32_t q = I.base + lane;
       if (d.srem[q] > rc.r) {
-        const uint32_t b = d.ci[q];
+        const uint32_t b = d.cix[q];
         e = d.eid[q];
         const size_t o = (size_t)I.y * d.W + (b >> 6);
         uint64_t word = Lh[o];
@@ -863,6 +862,7 @@ __global__ void k_advance(const Dev* __restrict__ devs) {
   c->r += 1;
   c->nR = c->nPush;
   c->nPush = 0;
+  d.status[2] = c->live;
   if (c->live == 0) {
     c->done = 1;
     d.status[0] = 1;
@@ -877,6 +877,60 @@ __global__ void k_post_init(Dev d) {
   if (c->err) c->done = 1;
   d.status[0] = c->err ? 2u : (c->done ? 1u : 0u);
   d.status[1] = 0;
+  d.status[2] = c->err ? 0u : c->live;
+}
+
+// ---- adjacency compaction (between rounds, host-triggered) --------------
+// Keep each row's live slots at its front, in order, so that later rounds
+// scan only live ones.  Runs only at a round boundary of a running slot:
+// both kernels see the same (finished / halted) state and do nothing then.
+__global__ void __launch_bounds__(256) k_compact_rows(Dev d) {
+  const Ctl* c = d.ctl;
+  if (c->done || c->halt) return;
+  const uint32_t lane = lane_id(), wpb = blockDim.x / WAVE;
+  for (uint32_t x = blockIdx.x * wpb + threadIdx.x / WAVE; x < d.n; x += gridDim.x * wpb) {
+    const uint32_t beg = d.rp[x], n = d.len[x];
+    uint32_t kept = 0;
+    for (uint32_t i0 = 0; i0 < n; i0 += WAVE) {
+      const uint32_t i = i0 + lane;
+      const bool live = i < n && d.srem[beg + i] == ALIVE;
+      const uint64_t bal = __ballot(live);
+      if (live) {
+        const uint32_t pos = kept + (uint32_t)__popcll(bal & ((1ull << lane) - 1));
+        d.tci[beg + pos] = d.cix[beg + i];
+        d.teid[beg + pos] = d.eid[beg + i];
+      }
+      kept += (uint32_t)__popcll(bal);
+    }
+    if (lane == 0) d.len[x] = kept;
+  }
+}
+
+__global__ void __launch_bounds__(256) k_compact_commit(Dev d) {
+  const Ctl* c = d.ctl;
+  if (c->done || c->halt) return;
+  const uint32_t lane = lane_id(), wpb = blockDim.x / WAVE;
+  for (uint32_t x = blockIdx.x * wpb + threadIdx.x / WAVE; x < d.n; x += gridDim.x * wpb) {
+    const uint32_t beg = d.rp[x], n = d.len[x];
+    for (uint32_t i = lane; i < n; i += WAVE) {
+      const uint32_t q = beg + i, y = d.tci[q], e = d.teid[q];
+      d.cix[q] = y;
+      d.eid[q] = e;
+      d.srem[q] = ALIVE;
+      if (y > x) d.s1[e] = q;
+      else d.s2[e] = q;
+    }
+  }
+}
+
+// Private adjacency copy and full rows, before the first round.
+__global__ void k_init_rows(Dev d) {
+  if (d.ctl->err) return;
+  for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < d.nnz;
+       i += (size_t)gridDim.x * blockDim.x)
+    d.cix[i] = d.ci[i];
+  for (uint32_t x = blockIdx.x * blockDim.x + threadIdx.x; x < d.n; x += gridDim.x * blockDim.x)
+    d.len[x] = d.rp[x + 1] - d.rp[x];
 }
 
 }  // namespace hotruss

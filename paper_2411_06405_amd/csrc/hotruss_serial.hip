@@ -20,11 +20,11 @@ __device__ __forceinline__ RoundCtx round_ctx(const Ctl* c) { return RoundCtx{c-
 // neighbourhood (the smaller) against the other's (j-1)-ball.
 __device__ bool reach_serial(const Dev& d, uint32_t j, uint32_t r, uint32_t x, uint32_t w) {
   uint32_t a = x, b = w;
-  if (d.rp[a + 1] - d.rp[a] > d.rp[b + 1] - d.rp[b]) { a = w; b = x; }
+  if (row_end(d, a) - d.rp[a] > row_end(d, b) - d.rp[b]) { a = w; b = x; }
   const uint64_t* P = d.L[j - 1];
   if (getbit(P, d.W, a, b)) return true;
-  for (uint32_t q = d.rp[a]; q < d.rp[a + 1]; ++q)
-    if (d.srem[q] > r && getbit(P, d.W, b, d.ci[q])) return true;
+  for (uint32_t q = d.rp[a]; q < row_end(d, a); ++q)
+    if (d.srem[q] > r && getbit(P, d.W, b, d.cix[q])) return true;
   return false;
 }
 
@@ -40,7 +40,7 @@ __device__ void drop_serial(const Dev& d, uint32_t j, const RoundCtx& rc, uint32
   // follow-up work for the next level (or the support update)
   const uint32_t list = (j == d.h) ? d.h + 1 : j + 1;
   const uint32_t base = d.rp[x];
-  const uint32_t deg = d.rp[x + 1] - base;
+  const uint32_t deg = row_end(d, x) - base;
   const uint32_t extra = (j == d.h) ? 0 : 1;
   const uint32_t nv = deg + extra;
   const uint32_t nch = (nv + CHUNK - 1) / CHUNK;
@@ -80,8 +80,8 @@ __global__ void __launch_bounds__(256) k_level_serial(const Dev* __restrict__ dp
       const uint32_t z = (it & 1) ? d.eu[e] : d.ev[e];
       if (j == 2) {
         if (lane == 0) test_serial(d, j, rc, x, z);
-        for (uint32_t q = d.rp[z] + lane; q < d.rp[z + 1]; q += WAVE)
-          if (d.srem[q] >= rc.r) test_serial(d, j, rc, x, d.ci[q]);
+        for (uint32_t q = d.rp[z] + lane; q < row_end(d, z); q += WAVE)
+          if (d.srem[q] >= rc.r) test_serial(d, j, rc, x, d.cix[q]);
       } else {
         for (uint32_t i = lane; i < d.W; i += WAVE) {
           uint64_t wd = row(d.L[j - 1], d.W, z)[i] | row(d.Dm[j - 1], d.W, z)[i];
@@ -96,8 +96,8 @@ __global__ void __launch_bounds__(256) k_level_serial(const Dev* __restrict__ dp
       const uint64_t zw = d.evl[j - 1][rc.p][it - A];
       const uint32_t z = (uint32_t)(zw >> 32), w = (uint32_t)zw;
       if (lane == 0) test_serial(d, j, rc, z, w);
-      for (uint32_t q = d.rp[z] + lane; q < d.rp[z + 1]; q += WAVE)
-        if (d.srem[q] > rc.r) test_serial(d, j, rc, d.ci[q], w);
+      for (uint32_t q = d.rp[z] + lane; q < row_end(d, z); q += WAVE)
+        if (d.srem[q] > rc.r) test_serial(d, j, rc, d.cix[q], w);
     } else {
       // row z of the change marks, one word at a time (wave-uniform loop)
       const uint32_t z = it - A;
@@ -108,8 +108,8 @@ __global__ void __launch_bounds__(256) k_level_serial(const Dev* __restrict__ dp
           wd &= wd - 1;
           const uint32_t w = i * 64 + b;
           if (lane == 0) test_serial(d, j, rc, z, w);
-          for (uint32_t q = d.rp[z] + lane; q < d.rp[z + 1]; q += WAVE)
-            if (d.srem[q] > rc.r) test_serial(d, j, rc, d.ci[q], w);
+          for (uint32_t q = d.rp[z] + lane; q < row_end(d, z); q += WAVE)
+            if (d.srem[q] > rc.r) test_serial(d, j, rc, d.cix[q], w);
         }
       }
     }
@@ -141,9 +141,9 @@ __global__ void __launch_bounds__(256) k_support_serial(const Dev* __restrict__ 
         const uint32_t w = scan ? i * 64 + bpos : (uint32_t)d.evl[h][rc.p][it];
         const uint64_t* Lw = row(d.L[h], d.W, w);
         const uint64_t* Dw = row(d.Dm[h], d.W, w);
-        for (uint32_t q = d.rp[a] + lane; q < d.rp[a + 1]; q += WAVE) {
+        for (uint32_t q = d.rp[a] + lane; q < row_end(d, a); q += WAVE) {
           if (d.srem[q] <= rc.r) continue;
-          const uint32_t bb = d.ci[q];
+          const uint32_t bb = d.cix[q];
           uint64_t word = Lw[bb >> 6];
           if (a < bb) word |= Dw[bb >> 6];
           if (!((word >> (bb & 63)) & 1ull)) continue;

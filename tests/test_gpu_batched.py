@@ -181,3 +181,12 @@ def test_session_budget_and_cancel():
         _submit(s, gen.complete(8), 4)
     assert e.value.status == -1
     s.close()
+
+
+def test_batched_row_compaction_every_launch_exact():
+    gs, hs = _mixed_small()
+    b = concat(gs, hs)
+    ts, rs = _ht().decompose_batch(b, tune={"flags": _ht()._lib.HO_FLAG_COMPACT_EACH})
+    for g, h, t, r in zip(gs, hs, ts, rs):
+        to, ro, _ = oracle.decompose(g, h)
+        assert np.array_equal(t, to) and np.array_equal(r, ro), (g.name, h)

@@ -149,3 +149,16 @@ def test_host_loop_equals_graph():
     assert st["kernel_ms"]["support_update"] > 0
     for x in (b, c):
         assert np.array_equal(a[0], x[0]) and np.array_equal(a[1], x[1])
+
+
+@pytest.mark.parametrize("h", [1, 2, 3])
+def test_row_compaction_every_launch_exact(h):
+    # live slots moved to the front of their rows between graph launches (and
+    # between host-driven rounds) at every chance: results unchanged
+    import paper_2411_06405_amd as ht
+    C = ht._lib.HO_FLAG_COMPACT_EACH
+    for g in (W.d1(1), W.d2(n=2000) if h < 3 else W.d2(n=1000), W.d3(scale=9)):
+        to, ro, _ = oracle.decompose(g, h)
+        for flags in (C, C | ht._lib.HO_FLAG_HOST_LOOP):
+            t, rho = run_gpu(g, h, tune={"flags": flags})
+            assert np.array_equal(t, to) and np.array_equal(rho, ro), (g.name, flags)
