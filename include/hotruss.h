@@ -93,6 +93,7 @@ typedef struct {
     uint64_t levels;        /* distinct levels k visited (level jumps)             */
     uint64_t events;        /* ball-change events at the top level h               */
     uint64_t overflows;     /* rounds in which a work list overflowed (serial path) */
+    uint64_t compactions;   /* adjacency compactions (live slots moved to the row fronts) */
     double   device_ms;     /* device time of the whole call (HIP events)          */
     /* HO_FLAG_STATS only: summed HIP-event time and launch count per kernel kind:
      * 0 initial h-support, 1 level-jump minimum, 2 peel/mark, 3 ball-change

@@ -41,7 +41,8 @@ class Tuning(C.Structure):
 
 class Stats(C.Structure):
     _fields_ = [("rounds", C.c_uint64), ("levels", C.c_uint64), ("events", C.c_uint64),
-                ("overflows", C.c_uint64), ("device_ms", C.c_double),
+                ("overflows", C.c_uint64), ("compactions", C.c_uint64),
+                ("device_ms", C.c_double),
                 ("kernel_ms", C.c_double * 6), ("kernel_launches", C.c_uint64 * 6),
                 ("work", C.c_uint64 * 8)]
 
@@ -171,7 +172,7 @@ def last_stats() -> dict:
     s = Stats()
     _check(lib.hoTrussLastStats(C.byref(s)), "hoTrussLastStats")
     return {"rounds": s.rounds, "levels": s.levels, "events": s.events,
-            "overflows": s.overflows, "device_ms": s.device_ms,
+            "overflows": s.overflows, "compactions": s.compactions, "device_ms": s.device_ms,
             "kernel_ms": dict(zip(KERNEL_KINDS, list(s.kernel_ms))),
             "kernel_launches": dict(zip(KERNEL_KINDS, list(s.kernel_launches))),
             "work": dict(zip(WORK_KINDS, list(s.work)))}

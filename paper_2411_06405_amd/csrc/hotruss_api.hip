@@ -278,6 +278,10 @@ void launch_step(const Dev* devs, uint32_t S, uint32_t hmax, const RoundGrid& g,
   hipLaunchKernelGGL(k_advance, dim3(1, S), dim3(64), 0, s, devs);
 }
 
+// Compact again once a tenth of the live edges have been peeled since the
+// last compaction (a compaction reads and writes the active slots once).
+uint32_t compact_next(uint32_t live) { return live - live / 10; }
+
 void launch_compact(const Dev& d, hipStream_t s) {
   const unsigned T = 256;
   const unsigned g = grid_for(d.n, T / WAVE);
@@ -579,7 +583,7 @@ class Engine {
       slot_dev[slot] = d;
       slot_since[slot] = steps;
       live_seen[slot] = 0;
-      compact_at[slot] = (uint32_t)(r.m / 2);
+      compact_at[slot] = compact_next((uint32_t)r.m);
       compact_each[slot] = r.has_tune && (r.tune.flags & HO_FLAG_COMPACT_EACH) ? 1 : 0;
       HOCHK(start_slot(d, r.has_tune ? &r.tune : nullptr, sup0, sup1));
     }
@@ -690,7 +694,7 @@ class Engine {
       if (slot_req[i] < 0 || live_seen[i] == 0) continue;
       if (!compact_each[i] && live_seen[i] > compact_at[i]) continue;
       launch_compact(slot_dev[i], s);
-      compact_at[i] = live_seen[i] / 2;
+      compact_at[i] = compact_next(live_seen[i]);
       live_seen[i] = 0;
     }
     HIPCHK(hipGetLastError());
@@ -769,11 +773,11 @@ hoStatus run_rounds_host(const Dev& d, const RoundGrid& g, hipStream_t s, bool t
   Ctl c;
   hoStatus st = read_ctl(d, &c, s);
   uint64_t rounds = 0;
-  uint32_t compact_at = d.m / 2;
+  uint32_t compact_at = compact_next(d.m);
   while (st == HO_OK && !c.done) {
     if (c.live <= compact_at || (d.serial & HO_FLAG_COMPACT_EACH)) {
       launch_compact(d, s);
-      compact_at = c.live / 2;
+      compact_at = compact_next(c.live);
     }
     if ((st = tm.begin(s)) != HO_OK) break;
     hipLaunchKernelGGL(k_jump_min, dim3(g.jump), dim3(T), 0, s, dp);
@@ -924,6 +928,7 @@ hoStatus hoTrussDecompose(const uint32_t* row_ptr, const uint32_t* col_idx, uint
   out.levels = c.levels;
   out.events = c.events;
   out.overflows = c.overflows;
+  out.compactions = c.compactions;
   out.device_ms = ms;
   for (uint32_t i = 0; i < NSTAT; ++i) out.work[i] = c.stat[i];
   t_stats = out;

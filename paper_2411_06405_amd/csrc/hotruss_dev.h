@@ -62,7 +62,8 @@ struct Ctl {
   uint32_t ovf[HMAX + 1][2];  // event list overflowed
   uint32_t nit[HMAX + 2];     // work items per level (index h+1: support items)
   uint32_t iovf[HMAX + 2];    // work item list overflowed
-  uint32_t pad[7];
+  uint32_t compactions;  // adjacency compactions done (statistics)
+  uint32_t pad[6];
   // stats mode: work counters, level kernel [0..5), support kernel [5..8)
   uint64_t stat[NSTAT];
 };

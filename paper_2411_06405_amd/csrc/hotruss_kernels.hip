@@ -646,10 +646,13 @@ __global__ void __launch_bounds__(LV_THREADS) k_level(const Dev* __restrict__ de
       }
     }
     const uint64_t bal = __ballot(have);
-    if (counting && lane == 0) {
-      if (it_taken) atomicAdd(&s_stat[0], 1u);
-      atomicAdd(&s_stat[1], (uint32_t)__popcll(__ballot(examined)));
-      atomicAdd(&s_stat[2], (uint32_t)__popcll(bal));
+    if (counting) {
+      const uint32_t nex = (uint32_t)__popcll(__ballot(examined));  // every lane votes
+      if (lane == 0) {
+        if (it_taken) atomicAdd(&s_stat[0], 1u);
+        atomicAdd(&s_stat[1], nex);
+        atomicAdd(&s_stat[2], (uint32_t)__popcll(bal));
+      }
     }
     uint32_t slot = 0;
     if (lane == 0 && bal) slot = atomicAdd(&s_count, (uint32_t)__popcll(bal));
@@ -907,8 +910,9 @@ __global__ void __launch_bounds__(256) k_compact_rows(Dev d) {
 }
 
 __global__ void __launch_bounds__(256) k_compact_commit(Dev d) {
-  const Ctl* c = d.ctl;
+  Ctl* c = d.ctl;
   if (c->done || c->halt) return;
+  if (blockIdx.x == 0 && threadIdx.x == 0) c->compactions += 1;
   const uint32_t lane = lane_id(), wpb = blockDim.x / WAVE;
   for (uint32_t x = blockIdx.x * wpb + threadIdx.x / WAVE; x < d.n; x += gridDim.x * wpb) {
     const uint32_t beg = d.rp[x], n = d.len[x];
