@@ -46,7 +46,7 @@ WORKLOADS = {
     "er200_h2": (lambda: W.d1(0), 2, "Erdos-Renyi G(200,0.05) seed=0, h=2"),
 }
 
-CPU_SAMPLE_N = 3000  # Chung-Lu sample the oracle decomposes completely
+CPU_SAMPLE_N = 4000  # Chung-Lu sample the oracle decomposes completely (about 10-30 s)
 
 # Algorithmic bytes per unit of work of the two chunked round kernels (each
 # access counted at its natural size, not as cache lines):
@@ -325,6 +325,8 @@ def run_serve(args) -> dict:
 
 
 def main(argv=None):
+    # the library reports progress of long calls on stderr (every 10 s at most)
+    os.environ.setdefault("HOTRUSS_PROGRESS", "1")
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)

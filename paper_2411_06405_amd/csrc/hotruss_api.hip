@@ -8,6 +8,9 @@
 #include <map>
 #include <new>
 #include <functional>
+#include <chrono>
+#include <cstdio>
+#include <cstdlib>
 
 #include "../../include/hotruss.h"
 #include "hotruss_dev.h"
@@ -718,10 +721,33 @@ class Engine {
   // Replay the step graph until no slot is active and the queue is empty
   // (or max_launches replays have been launched), two replays in flight, the
   // slots' status words copied to pinned memory after each.
+  // Progress on stderr for long calls (environment HOTRUSS_PROGRESS set): at
+  // most every 10 s, from the host loop that drives the work.
+  void report_progress(std::chrono::steady_clock::time_point& last) {
+    static const bool on = std::getenv("HOTRUSS_PROGRESS") != nullptr;
+    if (!on) return;
+    const auto now = std::chrono::steady_clock::now();
+    if (now - last < std::chrono::seconds(10)) return;
+    last = now;
+    uint32_t active = 0;
+    uint64_t live = 0;
+    for (uint32_t i = 0; i < S; ++i)
+      if (slot_req[i] >= 0) {
+        ++active;
+        live += live_seen[i];
+      }
+    size_t finished = 0;
+    for (const Request& r : reqs) finished += r.state >= 2;
+    std::fprintf(stderr, "[hotruss] %llu graph launches: %zu finished, %u running (%llu live edges), %zu queued\n",
+                 (unsigned long long)steps, finished, active, (unsigned long long)live, queue.size());
+    std::fflush(stderr);
+  }
+
   hoStatus run(uint64_t max_launches = UINT64_MAX) {
     HOCHK(admit());
     if (!busy()) return HO_OK;
     HOCHK(ensure_graphs());
+    auto last_report = std::chrono::steady_clock::now();
     uint64_t launched = 0;
     uint64_t buf_at[2] = {0, 0};
     int head = 0, inflight = 0;
@@ -750,6 +776,7 @@ class Engine {
         HOCHK(recover_halts());
       }
       HOCHK(admit());
+      report_progress(last_report);
       HOCHK(maybe_compact());
     }
     HIPCHK(hipStreamSynchronize(s));
