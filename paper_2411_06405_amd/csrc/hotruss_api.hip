@@ -65,9 +65,9 @@ bool make_plan(uint32_t n, uint64_t m, uint32_t h, const hoTuning* tune, bool fu
   // Lists are sized so that a round rarely overflows them (a round that does
   // runs its level or support step through the serial kernels, far slower).
   p.evcap = tune && tune->event_capacity ? tune->event_capacity
-                                         : clamp_cap(cap_factor * m, 1u << 16, 1u << 27);
+                                         : clamp_cap(cap_factor * m, 1u << 16, 1u << 28);
   p.itcap = tune && tune->item_capacity ? tune->item_capacity
-                                        : clamp_cap(cap_factor * m, 1u << 16, 1u << 27);
+                                        : clamp_cap(cap_factor * m, 1u << 16, 1u << 28);
   const size_t rowbytes = (size_t)p.W * 8;
   if (rowbytes > MAX_LDS_ROW) return false;  // rows are built in LDS
   size_t o = 0;
