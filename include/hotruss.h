@@ -74,17 +74,20 @@ typedef struct {
                                  (0 = by row width)                                      */
     uint32_t flags;           /* HO_FLAG_*                                               */
     uint32_t event_capacity;  /* per-level ball-change event list entries; a round that
-                                 overflows it falls back to full bitset scans (0 = auto)  */
+                                 overflows it re-creates the next step's work from the
+                                 change-mark bitsets (0 = auto)                          */
     uint32_t grid_blocks;     /* workgroups of the round driver (0 = auto)               */
     uint32_t item_capacity;   /* per-level work item list entries; a round that overflows
-                                 it takes the serial path (0 = auto)                      */
+                                 it re-runs that step in windows that fit (0 = auto)      */
 } hoTuning;
 
 #define HO_FLAG_HOST_LOOP 0x1u  /* drive peel rounds from the host, one round per
                                    launch sequence (debugging; slower)                */
 #define HO_FLAG_STATS 0x2u      /* time every kernel with HIP events (implies host loop) */
-#define HO_FLAG_SERIAL_LEVELS 0x4u   /* testing: always take the serial ball-change path */
-#define HO_FLAG_SERIAL_SUPPORT 0x8u  /* testing: always take the serial support path     */
+#define HO_FLAG_SERIAL_LEVELS 0x4u   /* testing: run every ball-change step the way a round
+                                        whose work list overflowed runs it (work items
+                                        re-created from their sources in windows, host-driven) */
+#define HO_FLAG_SERIAL_SUPPORT 0x8u  /* testing: the same for the support update step       */
 #define HO_FLAG_COMPACT_EACH 0x10u   /* testing: compact the adjacency rows at every chance  */
 
 /* Work counters of the last decomposition on this host thread. */
@@ -92,7 +95,7 @@ typedef struct {
     uint64_t rounds;        /* peel rounds that removed at least one edge          */
     uint64_t levels;        /* distinct levels k visited (level jumps)             */
     uint64_t events;        /* ball-change events at the top level h               */
-    uint64_t overflows;     /* rounds in which a work list overflowed (serial path) */
+    uint64_t overflows;     /* rounds in which a list overflowed (windowed re-run)    */
     uint64_t compactions;   /* adjacency compactions (live slots moved to the row fronts) */
     double   device_ms;     /* device time of the whole call (HIP events)          */
     /* HO_FLAG_STATS only: summed HIP-event time and launch count per kernel kind:

@@ -8,8 +8,7 @@ from pathlib import Path
 PKG = Path(__file__).resolve().parent
 ROOT = PKG.parent
 LIB = PKG / "libhotruss.so"
-# (source, optimisation level): the serial overflow kernels are built at -O1
-SOURCES = [(PKG / "csrc" / "hotruss_api.hip", "-O3"), (PKG / "csrc" / "hotruss_serial.hip", "-O1")]
+SOURCES = [(PKG / "csrc" / "hotruss_api.hip", "-O3")]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = ["--offload-arch=gfx950", "-std=c++17", "-fPIC",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",

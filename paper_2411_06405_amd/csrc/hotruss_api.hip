@@ -16,12 +16,6 @@
 #include "hotruss_dev.h"
 #include "hotruss_kernels.hip"
 
-namespace hotruss {
-// serial forms (hotruss_serial.hip, a separate translation unit)
-__global__ void k_level_serial(const Dev* __restrict__ dp, uint32_t j);
-__global__ void k_support_serial(const Dev* __restrict__ dp);
-}  // namespace hotruss
-
 // status words per engine slot: {done, halt, live edges, unused}
 #define HO_STATUS_WORDS 4
 
@@ -63,11 +57,14 @@ bool make_plan(uint32_t n, uint64_t m, uint32_t h, const hoTuning* tune, bool fu
   p.n = n; p.m = m; p.h = h; p.full = full;
   p.W = words_per_row(n);
   // Lists are sized so that a round rarely overflows them (a round that does
-  // runs its level or support step through the serial kernels, far slower).
+  // re-runs the overflowed step from the host in windows that fit).
   p.evcap = tune && tune->event_capacity ? tune->event_capacity
                                          : clamp_cap(cap_factor * m, 1u << 16, 1u << 28);
   p.itcap = tune && tune->item_capacity ? tune->item_capacity
                                         : clamp_cap(cap_factor * m, 1u << 16, 1u << 28);
+  // room for the items of any single source (two rows' worth, or a ball row's
+  // words), so that a round can always be re-run one source at a time
+  p.itcap = std::max<uint32_t>(p.itcap, 2 * ((n + CHUNK - 1) / CHUNK) + 4);
   const size_t rowbytes = (size_t)p.W * 8;
   if (rowbytes > MAX_LDS_ROW) return false;  // rows are built in LDS
   size_t o = 0;
@@ -320,17 +317,78 @@ struct StepTimer {
   }
 };
 
+// Recovery sources of a step (see k_fill_level / k_fill_support).
+uint64_t recovery_sources(const Dev& d, const Ctl& c, uint32_t step) {
+  const uint32_t p = c.r & 1;
+  const uint64_t nA = 2ull * c.nR;
+  if (step <= d.h) {
+    if (step == 2) return nA;
+    const uint64_t nB = c.ovf[step - 1][p] ? (uint64_t)d.n * d.W * 64
+                                           : std::min<uint64_t>(c.nev[step - 1][p], d.evcap);
+    return nA + nB;
+  }
+  if (c.ovf[d.h][p]) return (uint64_t)d.n * d.W * 64;
+  if (d.h == 1) return nA;
+  return std::min<uint64_t>(c.nev[d.h][p], d.evcap);
+}
+
+// Re-run one step (2..h: level, h+1: support update) of the current round
+// whose work list overflowed: its work items are re-created from their
+// sources a window at a time (halving the window whenever the list would
+// overflow again) and the ordinary step kernel runs on each window.
+hoStatus recover_step(const Dev& d, const RoundGrid& g, hipStream_t s, uint32_t step,
+                      StepTimer& tm) {
+  const unsigned T = 256;
+  const Dev* dp = d.self;
+  const uint32_t list = step;  // level j uses list j, the support update list h+1
+  Ctl c;
+  HOCHK(read_ctl(d, &c, s));
+  const uint64_t total = recovery_sources(d, c, step);
+  uint64_t lo = 0, win = std::max<uint64_t>(total, 1);
+  const unsigned fill_grid = (unsigned)std::max<uint64_t>(1, std::min<uint64_t>((total + T - 1) / T, (uint64_t)num_cu() * 16));
+  // at least one window, also when the step has no sources: the window start
+  // is what clears the halt
+  do {
+    const uint64_t hi = std::min(total, lo + win);
+    HOCHK(tm.begin(s));
+    hipLaunchKernelGGL(k_window_begin, dim3(1), dim3(64), 0, s, dp, list);
+    if (step <= d.h) hipLaunchKernelGGL(k_fill_level, dim3(fill_grid), dim3(T), 0, s, dp, step, lo, hi);
+    else hipLaunchKernelGGL(k_fill_support, dim3(fill_grid), dim3(T), 0, s, dp, lo, hi);
+    HOCHK(tm.end(s, step <= d.h ? KT_LEVEL : KT_SUPPORT));
+    HOCHK(read_ctl(d, &c, s));
+    if (c.iovf[list]) {
+      if (hi - lo == 1) return HO_ERR_INTERNAL;  // one source's items exceed the list
+      win = std::max<uint64_t>(1, (hi - lo) / 2);
+      continue;
+    }
+    HOCHK(tm.begin(s));
+    if (step <= d.h) hipLaunchKernelGGL(k_level, dim3(g.level), dim3(LV_THREADS), 0, s, dp, step);
+    else hipLaunchKernelGGL(k_support, dim3(g.support), dim3(T), 0, s, dp);
+    HOCHK(tm.end(s, step <= d.h ? KT_LEVEL : KT_SUPPORT));
+    if (d.spart) {
+      if (step <= d.h) hipLaunchKernelGGL(k_stats_fold, dim3(1), dim3(256), 0, s, dp, 0u, 5u, g.level);
+      else hipLaunchKernelGGL(k_stats_fold, dim3(1), dim3(256), 0, s, dp, 5u, 3u, g.support);
+    }
+    lo = hi;
+    win = std::min<uint64_t>(std::max<uint64_t>(total, 1), win * 2);
+  } while (lo < total);
+  hipLaunchKernelGGL(k_recovery_end, dim3(1), dim3(64), 0, s, dp);
+  HIPCHK(hipGetLastError());
+  return HO_OK;
+}
+
 // Run one slot's round steps from `from` on (2..h: level j, h+1: support
-// update) and end the round, from the host, taking the serial kernel for any
-// step whose chunked kernel halts on an overflowed work list.
+// update) and end the round, from the host; a step whose list kernel halts on
+// an overflowed work list (or every step from `from` when recover_first) is
+// re-run in windows by recover_step.
 hoStatus steps_host(const Dev& d, const RoundGrid& g, hipStream_t s, uint32_t from,
-                    bool serial_first, StepTimer& tm) {
+                    bool recover_first, StepTimer& tm) {
   const unsigned T = 256;
   const Dev* dp = d.self;
   Ctl c;
   for (uint32_t step = from; step <= d.h + 1; ++step) {
-    bool serial = serial_first && step == from;
-    if (!serial) {
+    bool recover = recover_first && step == from;
+    if (!recover) {
       HOCHK(tm.begin(s));
       if (step <= d.h) hipLaunchKernelGGL(k_level, dim3(g.level), dim3(LV_THREADS), 0, s, dp, step);
       else hipLaunchKernelGGL(k_support, dim3(g.support), dim3(T), 0, s, dp);
@@ -340,16 +398,9 @@ hoStatus steps_host(const Dev& d, const RoundGrid& g, hipStream_t s, uint32_t fr
         else hipLaunchKernelGGL(k_stats_fold, dim3(1), dim3(256), 0, s, dp, 5u, 3u, g.support);
       }
       HOCHK(read_ctl(d, &c, s));
-      serial = c.halt != 0;
+      recover = c.halt != 0;
     }
-    if (serial) {
-      HIPCHK(hipMemsetAsync(&d.ctl->halt, 0, sizeof(uint32_t), s));
-      HIPCHK(hipMemsetAsync(&d.status[1], 0, sizeof(uint32_t), s));  // host-driven, not captured
-      HOCHK(tm.begin(s));
-      if (step <= d.h) hipLaunchKernelGGL(k_level_serial, dim3(g.level), dim3(T), 0, s, dp, step);
-      else hipLaunchKernelGGL(k_support_serial, dim3(g.support), dim3(T), 0, s, dp);
-      HOCHK(tm.end(s, step <= d.h ? KT_LEVEL : KT_SUPPORT));
-    }
+    if (recover) HOCHK(recover_step(d, g, s, step, tm));
   }
   HOCHK(tm.begin(s));
   hipLaunchKernelGGL(k_advance, dim3(1), dim3(64), 0, s, dp);
@@ -713,7 +764,10 @@ class Engine {
       Ctl c;
       HOCHK(read_ctl(slot_dev[i], &c, s));
       if (!c.halt) continue;
+      if (c.halt_step < 2 || c.halt_step > slot_dev[i].h + 1) return HO_ERR_INTERNAL;
       HOCHK(steps_host(slot_dev[i], g, s, c.halt_step, true, tm));
+      HOCHK(read_ctl(slot_dev[i], &c, s));
+      if (c.halt) return HO_ERR_INTERNAL;  // the round must have ended
     }
     return HO_OK;
   }
@@ -751,10 +805,14 @@ class Engine {
     uint64_t launched = 0;
     uint64_t buf_at[2] = {0, 0};
     int head = 0, inflight = 0;
+    int calm = 2;  // graph launches since the last halt (saturating)
     while (true) {
       while (inflight < 2 && busy() && launched < max_launches) {
         const int buf = (head + inflight) & 1;
-        const int which = plain ? (steps == 0 ? 0 : steps < 4 ? 1 : 2) : (queue.empty() ? 2 : 1);
+        // short graphs right after a halt (overflowing rounds tend to come in
+        // runs, and every round after a halt in the same graph is skipped)
+        const int which = calm < 2 ? 0
+                          : plain ? (steps == 0 ? 0 : steps < 4 ? 1 : 2) : (queue.empty() ? 2 : 1);
         HIPCHK(hipGraphLaunch(exec[which], s));
         HIPCHK(hipMemcpyAsync(hstat + HO_STATUS_WORDS * S * buf, status_d,
                               4ull * HO_STATUS_WORDS * S, hipMemcpyDeviceToHost, s));
@@ -774,6 +832,9 @@ class Engine {
         inflight = 0;
         head = 0;
         HOCHK(recover_halts());
+        calm = 0;
+      } else if (calm < 2) {
+        ++calm;
       }
       HOCHK(admit());
       report_progress(last_report);

@@ -53,7 +53,7 @@ struct Ctl {
   uint32_t live;     // edges still in S
   uint32_t levels;   // levels visited
   uint32_t done;     // decomposition finished (read by the host with halt)
-  uint32_t halt;     // a work list overflowed: the host finishes this round
+  uint32_t halt;     // a work list overflowed: the host re-runs the step in windows
   uint32_t halt_step;  // step that halted: level j (2..h), or h+1 for the support update
   uint32_t jump;     // this round starts with a level jump
   uint64_t events;   // top-level ball-change events (statistics)
@@ -63,7 +63,8 @@ struct Ctl {
   uint32_t nit[HMAX + 2];     // work items per level (index h+1: support items)
   uint32_t iovf[HMAX + 2];    // work item list overflowed
   uint32_t compactions;  // adjacency compactions done (statistics)
-  uint32_t pad[6];
+  uint32_t recovering;   // the host is re-running an overflowed step in windows
+  uint32_t pad[5];
   // stats mode: work counters, level kernel [0..5), support kernel [5..8)
   uint64_t stat[NSTAT];
 };
@@ -77,8 +78,8 @@ struct Dev {
   uint32_t evcap;       // capacity of each level>=2 event list
   uint32_t itcap;       // capacity of each work item list
   uint32_t nminpart;    // blocks of the level-jump minimum kernel
-  uint32_t serial;      // testing: bit 2 forces the serial level path, bit 3 the serial
-                        // support path, bit 4 compacts rows at every chance
+  uint32_t serial;      // testing: bit 2 forces the windowed re-run of every level step,
+                        // bit 3 of every support step, bit 4 compacts rows at every chance
   uint32_t* eid;        // slot -> edge id           [2m]
   uint32_t* eu;         // edge id -> lower endpoint  [m]
   uint32_t* ev;         // edge id -> upper endpoint  [m]

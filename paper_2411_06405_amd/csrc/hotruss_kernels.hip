@@ -541,7 +541,7 @@ __global__ void __launch_bounds__(LV_THREADS) k_level(const Dev* __restrict__ de
   // a round that peels every remaining edge leaves no ball or support that
   // could matter: the decomposition ends with it
   if (c->nR == c->live) return;
-  if (c->iovf[j] || (d.serial & 4u)) {
+  if (!c->recovering && (c->iovf[j] || (d.serial & 4u))) {
     // work list overflowed: leave this level to the serial kernel the host runs
     if (blockIdx.x == 0 && threadIdx.x == 0) {
       c->halt = 1;
@@ -765,7 +765,7 @@ __global__ void __launch_bounds__(256) k_support(const Dev* __restrict__ devs) {
   const uint32_t list = d.h + 1;
   if (c->halt) return;
   if (c->nR == c->live) return;  // the last round: nothing left to update
-  if (c->iovf[list] || (d.serial & 8u)) {
+  if (!c->recovering && (c->iovf[list] || (d.serial & 8u))) {
     if (blockIdx.x == 0 && threadIdx.x == 0) {
       c->halt = 1;
       c->halt_step = list;
@@ -881,6 +881,162 @@ __global__ void k_post_init(Dev d) {
   d.status[0] = c->err ? 2u : (c->done ? 1u : 0u);
   d.status[1] = 0;
   d.status[2] = c->err ? 0u : c->live;
+}
+
+// ---- recovery of a round whose work list overflowed ----------------------
+// The host re-creates the work items of the overflowed step from their
+// sources, a window of sources at a time small enough for the list, and
+// runs the ordinary step kernel on each window.  Re-testing a pair is
+// harmless: pairs that already left fail the ball-bit filter.  Sources of
+// level j: the directed removals x-lost-z of the round (index < 2|R|), then
+// the level-(j-1) events from their list, or, when that list overflowed,
+// the bits of the level-(j-1) change marks (row-major, 64 per word).
+
+// Follow-up items of the event (x -> w) at list `list` (all lanes call).
+__device__ __forceinline__ void fill_event_items(const Dev& d, uint32_t list, bool support,
+                                                 bool has, uint32_t x, uint32_t w) {
+  uint32_t bx = 0, nx = 0;
+  if (has) {
+    bx = d.rp[x];
+    nx = d.len[x] + (support ? 0u : 1u);
+  }
+  const uint32_t nch = (nx + CHUNK - 1) / CHUNK;
+  const uint32_t slot = wave_reserve(&d.ctl->nit[list], nch);
+  if (support) {
+    for (uint32_t q = 0; q < nch; ++q) {
+      if (slot + q < d.itcap)
+        d.itl[list][slot + q] = Item{x, w, bx + q * CHUNK, item_meta(0, 0, min(CHUNK, nx - q * CHUNK), 0)};
+      else d.ctl->iovf[list] = 1;
+    }
+  } else {
+    put_row_items(d, list, slot, nch, KIND_B_SLOTS, x, w, bx, nx, 1);
+  }
+}
+
+// Change-mark bits [blo, bhi) of level jm as events (x -> w): follow-up
+// items at `list` (support items when `support`).
+__device__ void fill_from_marks(const Dev& d, uint32_t jm, uint32_t list, bool support,
+                                uint64_t blo, uint64_t bhi) {
+  if (blo >= bhi) return;
+  const uint64_t wlo = blo / 64, whi = (bhi + 63) / 64;
+  const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+  for (uint64_t wb = wlo + blockIdx.x * (uint64_t)blockDim.x + (threadIdx.x & ~(WAVE - 1)); wb < whi;
+       wb += stride) {
+    const uint64_t kw = wb + lane_id();
+    uint64_t wd = 0;
+    uint32_t x = 0, word = 0;
+    if (kw < whi) {
+      x = (uint32_t)(kw / d.W);
+      word = (uint32_t)(kw % d.W);
+      wd = row(d.Dm[jm], d.W, x)[word];
+      if (kw == wlo && (blo & 63)) wd &= ~0ull << (blo & 63);
+      if (kw == whi - 1 && (bhi & 63)) wd &= (1ull << (bhi & 63)) - 1;
+    }
+    while (__ballot(wd != 0)) {
+      const bool has = wd != 0;
+      uint32_t w = 0;
+      if (has) {
+        w = word * 64 + (uint32_t)(__ffsll((unsigned long long)wd) - 1);
+        wd &= wd - 1;
+      }
+      fill_event_items(d, list, support, has, x, w);
+    }
+  }
+}
+
+// Listed events [elo, ehi) of level je (or the directed removals when
+// `removals`): follow-up items at `list`.
+__device__ void fill_from_list(const Dev& d, uint32_t je, bool removals, uint32_t p,
+                               uint32_t list, bool support, uint64_t elo, uint64_t ehi) {
+  const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+  for (uint64_t b = elo + blockIdx.x * (uint64_t)blockDim.x + (threadIdx.x & ~(WAVE - 1)); b < ehi;
+       b += stride) {
+    const uint64_t i = b + lane_id();
+    const bool has = i < ehi;
+    uint32_t x = 0, w = 0;
+    if (has) {
+      if (removals) {
+        const uint32_t e = d.R[p][i >> 1];
+        x = (i & 1) ? d.ev[e] : d.eu[e];
+        w = (i & 1) ? d.eu[e] : d.ev[e];
+      } else {
+        const uint64_t xw = d.evl[je][p][i];
+        x = (uint32_t)(xw >> 32);
+        w = (uint32_t)xw;
+      }
+    }
+    fill_event_items(d, list, support, has, x, w);
+  }
+}
+
+__global__ void __launch_bounds__(256) k_fill_level(const Dev* __restrict__ dp, uint32_t j,
+                                                    uint64_t lo, uint64_t hi) {
+  const Dev& d = *dp;
+  const Ctl* c = d.ctl;
+  const RoundCtx rc = round_ctx(c);
+  const uint64_t nA = 2ull * c->nR;
+  // the directed removals x-lost-z
+  const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+  const uint64_t ahi = min(hi, nA);
+  for (uint64_t b = lo + blockIdx.x * (uint64_t)blockDim.x + (threadIdx.x & ~(WAVE - 1)); b < ahi;
+       b += stride) {
+    const uint64_t src = b + lane_id();
+    const bool a = src < ahi;
+    uint32_t x = 0, z = 0;
+    if (a) {
+      const uint32_t e = d.R[rc.p][src >> 1];
+      x = (src & 1) ? d.ev[e] : d.eu[e];
+      z = (src & 1) ? d.eu[e] : d.ev[e];
+    }
+    if (j == 2) {
+      // (x, y), y an old neighbour of z, and (x, z); (y, z), y a live neighbour of x
+      uint32_t bz = 0, dz = 0, bx = 0, dx = 0;
+      if (a) {
+        bz = d.rp[z];
+        dz = d.len[z];
+        bx = d.rp[x];
+        dx = d.len[x];
+      }
+      const uint32_t n0 = a ? (dz + CHUNK) / CHUNK : 0, n1 = a ? (dx + CHUNK - 1) / CHUNK : 0;
+      const uint32_t slot = wave_reserve(&d.ctl->nit[2], n0 + n1);
+      put_row_items(d, 2, slot, n0, KIND_A_SLOTS, x, z, bz, dz + 1, 1);
+      put_row_items(d, 2, slot + n0, n1, KIND_B_SLOTS, x, z, bx, dx, 0);
+    } else {
+      emit_word_items(d, j, a, x, z);  // (x, w), w in z's old (j-1)-ball
+    }
+  }
+  // the level-(j-1) events (x -> w): (y, w), y a live neighbour of x, and (x, w)
+  if (j == 2 || hi <= nA) return;
+  const uint64_t blo = lo > nA ? lo - nA : 0, bhi = hi - nA;
+  if (c->ovf[j - 1][rc.p]) fill_from_marks(d, j - 1, j, false, blo, bhi);
+  else fill_from_list(d, j - 1, false, rc.p, j, false, blo, bhi);
+}
+
+// Support items of the top-level events (listed, or the bits of the
+// top-level change marks); for h = 1 the events are the directed removals.
+__global__ void __launch_bounds__(256) k_fill_support(const Dev* __restrict__ dp, uint64_t lo,
+                                                      uint64_t hi) {
+  const Dev& d = *dp;
+  const Ctl* c = d.ctl;
+  const RoundCtx rc = round_ctx(c);
+  if (c->ovf[d.h][rc.p]) fill_from_marks(d, d.h, d.h + 1, true, lo, hi);
+  else fill_from_list(d, d.h, d.h == 1, rc.p, d.h + 1, true, lo, hi);
+}
+
+// Start of a recovery window: the step's work list is empty again.
+__global__ void k_window_begin(const Dev* __restrict__ dp, uint32_t list) {
+  if (blockIdx.x != 0 || threadIdx.x != 0) return;
+  Ctl* c = dp->ctl;
+  c->nit[list] = 0;
+  c->iovf[list] = 0;
+  c->halt = 0;
+  c->recovering = 1;
+  dp->status[1] = 0;
+}
+
+__global__ void k_recovery_end(const Dev* __restrict__ dp) {
+  if (blockIdx.x != 0 || threadIdx.x != 0) return;
+  dp->ctl->recovering = 0;
 }
 
 // ---- adjacency compaction (between rounds, host-triggered) --------------

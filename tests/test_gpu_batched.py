@@ -90,8 +90,13 @@ def test_batched_one_slot_at_a_time():
 @pytest.mark.parametrize("tune", [{"item_capacity": 64, "event_capacity": 64},
                                   {"flags": 0x4 | 0x8}])
 def test_batched_overflow_and_serial_slots_exact(tune):
-    # per-slot halts and host-finished rounds while other slots keep going
+    # per-slot halts and host-finished rounds (the windowed re-run of an
+    # overflowed step) while other slots keep going
     gs, hs = _mixed_small()
+    if "flags" in tune:  # every step of every round re-run from the host: keep it small
+        keep = [i for i, g in enumerate(gs) if g.m <= 2000][:8]
+        gs, hs = [gs[i] for i in keep], [hs[i] for i in keep]
+    print(f"[gpu] batched B={len(gs)} {tune}", flush=True)
     b = concat(gs, hs)
     ts, rs = _ht().decompose_batch(b, tune=tune)
     for g, h, t, r in zip(gs, hs, ts, rs):

@@ -162,3 +162,16 @@ def test_row_compaction_every_launch_exact(h):
         for flags in (C, C | ht._lib.HO_FLAG_HOST_LOOP):
             t, rho = run_gpu(g, h, tune={"flags": flags})
             assert np.array_equal(t, to) and np.array_equal(rho, ro), (g.name, flags)
+
+
+@pytest.mark.parametrize("h", [1, 2, 3])
+def test_forced_recovery_with_empty_steps_exact(h):
+    # every step re-run from the host, including steps with nothing to do
+    # (no events at a level, no support updates) in some rounds
+    import paper_2411_06405_amd as ht
+    L, S = ht._lib.HO_FLAG_SERIAL_LEVELS, ht._lib.HO_FLAG_SERIAL_SUPPORT
+    for g in (W.d1(0), gen.cycle(9), gen.complete(6), gen.star(5), gen.path(4)):
+        to, ro, _ = oracle.decompose(g, h)
+        for flags in (L | S, S, (L | S) | ht._lib.HO_FLAG_HOST_LOOP):
+            t, rho = run_gpu(g, h, tune={"flags": flags})
+            assert np.array_equal(t, to) and np.array_equal(rho, ro), (g.name, flags)
