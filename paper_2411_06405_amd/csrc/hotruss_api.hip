@@ -184,6 +184,17 @@ Dev carve(const Plan& p, void* ws, const uint32_t* rp, const uint32_t* ci, uint3
 
 thread_local hoStats t_stats;
 
+// A HIP event destroyed with its scope.
+struct EventGuard {
+  hipEvent_t e = nullptr;
+  EventGuard() = default;
+  EventGuard(const EventGuard&) = delete;
+  EventGuard& operator=(const EventGuard&) = delete;
+  ~EventGuard() {
+    if (e) (void)hipEventDestroy(e);
+  }
+};
+
 #define HIPCHK(x)                             \
   do {                                        \
     if ((x) != hipSuccess) return HO_ERR_HIP; \
@@ -854,9 +865,12 @@ hoStatus run_rounds_host(const Dev& d, const RoundGrid& g, hipStream_t s, bool t
   tm.on = timed;
   tm.kms = kms;
   tm.kl = klaunch;
+  EventGuard g0, g1;
   if (timed) {
-    HIPCHK(hipEventCreate(&tm.e0));
-    HIPCHK(hipEventCreate(&tm.e1));
+    HIPCHK(hipEventCreate(&g0.e));
+    HIPCHK(hipEventCreate(&g1.e));
+    tm.e0 = g0.e;
+    tm.e1 = g1.e;
   }
   Ctl c;
   hoStatus st = read_ctl(d, &c, s);
@@ -876,10 +890,6 @@ hoStatus run_rounds_host(const Dev& d, const RoundGrid& g, hipStream_t s, bool t
     st = steps_host(d, g, s, 2, false, tm);
     if (st == HO_OK) st = read_ctl(d, &c, s);
     if (++rounds > (uint64_t)d.m + 2) st = HO_ERR_INTERNAL;
-  }
-  if (timed) {
-    (void)hipEventDestroy(tm.e0);
-    (void)hipEventDestroy(tm.e1);
   }
   return st;
 }
@@ -971,27 +981,25 @@ hoStatus hoTrussDecompose(const uint32_t* row_ptr, const uint32_t* col_idx, uint
   if (st == HO_ERR_BUDGET) return HO_ERR_WORKSPACE;
   HOCHK(st);
   hoStats out{};
-  hipEvent_t ev0, ev1, es0 = nullptr, es1 = nullptr;
-  HIPCHK(hipEventCreate(&ev0));
-  HIPCHK(hipEventCreate(&ev1));
+  EventGuard ev0, ev1, es0, es1;  // destroyed on every return path
+  HIPCHK(hipEventCreate(&ev0.e));
+  HIPCHK(hipEventCreate(&ev1.e));
   if (stats) {
-    HIPCHK(hipEventCreate(&es0));
-    HIPCHK(hipEventCreate(&es1));
+    HIPCHK(hipEventCreate(&es0.e));
+    HIPCHK(hipEventCreate(&es1.e));
   }
-  HIPCHK(hipEventRecord(ev0, stream));
+  HIPCHK(hipEventRecord(ev0.e, stream));
   if (host_loop) {
-    HOCHK(eng.admit(es0, es1));
+    HOCHK(eng.admit(es0.e, es1.e));
     Dev d = eng.slot_dev[0];
     Ctl c;
     HOCHK(read_ctl(d, &c, stream));
     if (c.err) return HO_ERR_BAD_CSR;
     if (stats) {
       float ms = 0;
-      HIPCHK(hipEventElapsedTime(&ms, es0, es1));
+      HIPCHK(hipEventElapsedTime(&ms, es0.e, es1.e));
       out.kernel_ms[KT_SUPINIT] = ms;
       out.kernel_launches[KT_SUPINIT] = 1;
-      (void)hipEventDestroy(es0);
-      (void)hipEventDestroy(es1);
       d.spart = eng.spart_d;
       HIPCHK(hipMemsetAsync(d.spart, 0, 4ull * NSTAT * STAT_GRID, stream));
       HIPCHK(hipMemcpyAsync(d.self, &d, sizeof(Dev), hipMemcpyHostToDevice, stream));
@@ -1002,12 +1010,10 @@ hoStatus hoTrussDecompose(const uint32_t* row_ptr, const uint32_t* col_idx, uint
     if (eng.reqs[id].state != 2) return HO_ERR_INTERNAL;
     HOCHK(eng.reqs[id].result);
   }
-  HIPCHK(hipEventRecord(ev1, stream));
-  HIPCHK(hipEventSynchronize(ev1));
+  HIPCHK(hipEventRecord(ev1.e, stream));
+  HIPCHK(hipEventSynchronize(ev1.e));
   float ms = 0;
-  HIPCHK(hipEventElapsedTime(&ms, ev0, ev1));
-  (void)hipEventDestroy(ev0);
-  (void)hipEventDestroy(ev1);
+  HIPCHK(hipEventElapsedTime(&ms, ev0.e, ev1.e));
   Ctl c;
   HOCHK(read_ctl(eng.slot_dev[0], &c, stream));
   if (c.err) return HO_ERR_BAD_CSR;
