@@ -212,6 +212,21 @@ hoStatus hoPoll(hoSession *s, uint64_t ticket, int *done);
 hoStatus hoCancel(hoSession *s, uint64_t ticket);
 hoStatus hoSessionDestroy(hoSession *s);
 
+/* (k,h)-truss extraction: the (k,h)-truss is the edge set {e : t(e,h) >= k}
+ * (Def. 4; trusses are nested, so one decomposition answers every k).
+ * Given the trussness of every edge (device, uint32 [m], as written by
+ * hoTrussDecompose) and k, writes for each edge of the truss the smallest
+ * vertex id of its connected component in the truss, and UINT32_MAX for the
+ * edges below k (out_component, device, uint32 [m]); *out_count (host)
+ * receives the number of components.  Validates the CSR like the other
+ * entry points; returns after the work has completed.  The workspace
+ * (hoTrussComponentsWorkspaceBytes, about 32m + 8n bytes) is the caller's. */
+size_t hoTrussComponentsWorkspaceBytes(uint32_t n, uint64_t m);
+hoStatus hoTrussComponents(const uint32_t *row_ptr, const uint32_t *col_idx, uint32_t n, uint64_t m,
+                           const uint32_t *trussness, uint32_t k, uint32_t *out_component,
+                           uint32_t *out_count, void *workspace, size_t workspace_bytes,
+                           hipStream_t stream);
+
 const char *hoStatusString(hoStatus s);
 
 #ifdef __cplusplus

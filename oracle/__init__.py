@@ -8,7 +8,8 @@ library (``paper_2411_06405_amd``) and never imports it.
 from .oracle import (OracleError, build, certify, decompose, h_support, h_support_edges,
                      lib_path)
 from .brute import brute_trussness, brute_h_support
+from .components import truss_components
 
 __all__ = ["OracleError", "build", "certify", "decompose", "h_support", "h_support_edges",
            "lib_path",
-           "brute_trussness", "brute_h_support"]
+           "brute_trussness", "brute_h_support", "truss_components"]

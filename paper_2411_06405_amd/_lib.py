@@ -80,6 +80,10 @@ def _declare(lib):
     lib.hoCancel.argtypes = [vp, u64]
     lib.hoCancel.restype = C.c_int
     lib.hoSessionDestroy.argtypes = [vp]
+    lib.hoTrussComponentsWorkspaceBytes.argtypes = [u32, u64]
+    lib.hoTrussComponentsWorkspaceBytes.restype = sz
+    lib.hoTrussComponents.argtypes = [vp, vp, u32, u64, vp, u32, vp, C.POINTER(u32), vp, sz, vp]
+    lib.hoTrussComponents.restype = C.c_int
     lib.hoSessionDestroy.restype = C.c_int
     return lib
 
@@ -96,7 +100,7 @@ lib = load()
 EXPORTS = ["hoStatusString", "hoTrussWorkspaceBytes", "hoTrussHSupport", "hoTrussDecompose",
            "hoTrussLastStats", "hoTrussBatchedWorkspaceBytes", "hoTrussDecomposeBatched",
            "hoSessionCreate", "hoSubmit", "hoSessionProgress", "hoPoll", "hoCancel",
-           "hoSessionDestroy"]
+           "hoSessionDestroy", "hoTrussComponentsWorkspaceBytes", "hoTrussComponents"]
 
 
 def _check(rc: int, what: str):
@@ -190,6 +194,34 @@ def decompose_graph(g, h: int, **kw):
 
 def h_support_graph(g, h: int, **kw) -> np.ndarray:
     return to_numpy_u32(h_support(g.row_ptr, g.col_idx, g.n, h, **kw))
+
+
+def truss_components(row_ptr, col_idx, n: int, trussness, k: int, workspace=None, stream=None,
+                     device="cuda"):
+    """(k,h)-truss extraction: (label per edge, number of components).
+
+    label[e] (device int32 tensor holding uint32 values) is the smallest vertex
+    of e's component among the edges with t(e) >= k, 0xFFFFFFFF below k."""
+    rp = _dev_u32(row_ptr, device)
+    ci = _dev_u32(col_idx, device)
+    t = _dev_u32(trussness, device)
+    m = ci.numel() // 2
+    out = torch.empty(max(m, 1), dtype=torch.int32, device=device)
+    if workspace is None:
+        nb = int(lib.hoTrussComponentsWorkspaceBytes(n, m))
+        workspace = torch.empty(max(nb, 1), dtype=torch.uint8, device=device)
+    count = C.c_uint32()
+    rc = lib.hoTrussComponents(rp.data_ptr(), ci.data_ptr(), n, m, t.data_ptr(), int(k),
+                               out.data_ptr(), C.byref(count), workspace.data_ptr(),
+                               workspace.numel(), _stream(stream))
+    _check(rc, "hoTrussComponents")
+    return out[:m], int(count.value)
+
+
+def truss_components_graph(g, trussness, k: int, **kw):
+    """Convenience for host graphs: numpy uint32 labels and the count."""
+    lab, c = truss_components(g.row_ptr, g.col_idx, g.n, trussness, k, **kw)
+    return to_numpy_u32(lab), c
 
 
 def _host_ptr(a: np.ndarray, dtype) -> tuple:

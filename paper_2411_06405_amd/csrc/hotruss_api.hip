@@ -109,6 +109,39 @@ bool make_plan(uint32_t n, uint64_t m, uint32_t h, const hoTuning* tune, bool fu
   return true;
 }
 
+// Workspace of the truss extraction: validation state, edge ids, and the
+// union-find arrays (parent, touched) plus a counter, after the plan.
+bool make_topo_plan(uint32_t n, uint64_t m, Plan* P, size_t* off_cc) {
+  if (m >= (1ull << 31) || n == 0xffffffffu) return false;
+  Plan p;
+  p.n = n; p.m = m; p.h = 0; p.full = false;
+  p.W = words_per_row(n);
+  size_t o = 0;
+  auto take = [&](size_t bytes) { size_t r = o; o += up(bytes); return r; };
+  p.off_ctl = take(sizeof(Ctl));
+  p.off_eid = take(8 * m + 4);
+  p.off_eu = take(4 * m + 4);
+  p.off_ev = take(4 * m + 4);
+  p.off_s1 = take(4 * m + 4);
+  p.off_s2 = take(4 * m + 4);
+  p.off_srem = take(8 * m + 4);
+  p.off_upcnt = take(4 * (size_t)n + 4);
+  p.off_upoff = take(4 * (size_t)n + 4);
+  p.off_scan = take(4 * ((size_t)n / 1024 + 2));
+  p.off_minpart = take(4 * MIN_PART);
+  p.off_sup = take(4 * m + 4);
+  p.off_rho = p.off_R0 = p.off_R1 = p.off_cix = p.off_len = p.off_tci = p.off_teid = 0;
+  for (uint32_t j = 0; j <= HMAX; ++j) {
+    p.off_L[j] = p.off_Dm[j] = 0;
+    p.off_evl[j][0] = p.off_evl[j][1] = 0;
+  }
+  for (uint32_t j = 0; j <= HMAX + 1; ++j) p.off_itl[j] = 0;
+  *off_cc = take(8 * (size_t)n + 64);  // parent [n], touched [n], counter
+  p.total = o + ALIGN;
+  *P = p;
+  return true;
+}
+
 int g_num_cu = 0;
 std::once_flag g_once;
 
@@ -207,8 +240,8 @@ struct EventGuard {
   } while (0)
 
 // Canonical edge ids, ball build and initial h-support into out_sup.
-hoStatus run_init(const Dev& d, uint32_t* out_sup, const hoTuning* tune, hipStream_t s,
-                  hipEvent_t sup0 = nullptr, hipEvent_t sup1 = nullptr) {
+// CSR validation and canonical edge ids (slot <-> edge maps).
+void run_topology(const Dev& d, hipStream_t s) {
   const unsigned T = 256;
   hipLaunchKernelGGL(k_init_ctl, dim3(1), dim3(64), 0, s, d.ctl, d.m);
   hipLaunchKernelGGL(k_check_rowptr, dim3(grid_for(d.n + 1, T)), dim3(T), 0, s, d);
@@ -219,6 +252,12 @@ hoStatus run_init(const Dev& d, uint32_t* out_sup, const hoTuning* tune, hipStre
   hipLaunchKernelGGL(k_scan2, dim3(1), dim3(64), 0, s, d.scan_tmp, nb);
   hipLaunchKernelGGL(k_scan3, dim3(grid_for(d.n, T)), dim3(T), 0, s, d.up_off, d.scan_tmp, d.n);
   hipLaunchKernelGGL(k_edge_ids, dim3(grid_for(d.n, T / WAVE)), dim3(T), 0, s, d);
+}
+
+hoStatus run_init(const Dev& d, uint32_t* out_sup, const hoTuning* tune, hipStream_t s,
+                  hipEvent_t sup0 = nullptr, hipEvent_t sup1 = nullptr) {
+  const unsigned T = 256;
+  run_topology(d, s);
   const size_t lds = (size_t)d.W * 8;
   const unsigned rows_grid = grid_for(d.n, 1, 64);
   hipLaunchKernelGGL(k_build_L1, dim3(rows_grid), dim3(T), lds, s, d);
@@ -1214,6 +1253,54 @@ hoStatus hoSessionDestroy(hoSession* ss) {
     (void)hipStreamSynchronize(ss->eng.s);
   }
   delete ss;
+  return HO_OK;
+}
+
+// ------------------------------------------------------ truss extraction
+size_t hoTrussComponentsWorkspaceBytes(uint32_t n, uint64_t m) {
+  Plan p;
+  size_t off_cc;
+  if (!make_topo_plan(n, m, &p, &off_cc)) return 0;
+  return p.total;
+}
+
+hoStatus hoTrussComponents(const uint32_t* row_ptr, const uint32_t* col_idx, uint32_t n, uint64_t m,
+                           const uint32_t* trussness, uint32_t k, uint32_t* out_component,
+                           uint32_t* out_count, void* workspace, size_t workspace_bytes,
+                           hipStream_t stream) {
+  if (!out_count) return HO_ERR_INVALID_ARG;
+  if (m >= (1ull << 31)) return HO_ERR_INVALID_ARG;
+  if (m == 0) {
+    *out_count = 0;
+    return HO_OK;
+  }
+  if (!row_ptr || !col_idx || !trussness || !out_component || !workspace || n == 0)
+    return HO_ERR_INVALID_ARG;
+  Plan p;
+  size_t off_cc;
+  if (!make_topo_plan(n, m, &p, &off_cc)) return HO_ERR_INVALID_ARG;
+  if (workspace_bytes < p.total) return HO_ERR_WORKSPACE;
+  Dev d = carve(p, workspace, row_ptr, col_idx, nullptr, nullptr);
+  const uintptr_t base = ((uintptr_t)workspace + ALIGN - 1) / ALIGN * ALIGN;
+  uint32_t* parent = (uint32_t*)(base + off_cc);
+  uint32_t* touched = parent + n;
+  uint32_t* counter = touched + n;
+  const unsigned T = 256;
+  run_topology(d, stream);
+  hipLaunchKernelGGL(k_cc_init, dim3(grid_for(n, T)), dim3(T), 0, stream, parent, touched, n);
+  HIPCHK(hipMemsetAsync(counter, 0, sizeof(uint32_t), stream));
+  hipLaunchKernelGGL(k_cc_hook, dim3(grid_for(m, T)), dim3(T), 0, stream, d, trussness, k, parent,
+                     touched);
+  hipLaunchKernelGGL(k_cc_label, dim3(grid_for(std::max<uint64_t>(m, n), T)), dim3(T), 0, stream, d,
+                     trussness, k, parent, touched, out_component, counter);
+  HIPCHK(hipGetLastError());
+  Ctl c;
+  HOCHK(read_ctl(d, &c, stream));
+  if (c.err) return HO_ERR_BAD_CSR;
+  uint32_t cnt = 0;
+  HIPCHK(hipMemcpyAsync(&cnt, counter, sizeof(uint32_t), hipMemcpyDeviceToHost, stream));
+  HIPCHK(hipStreamSynchronize(stream));
+  *out_count = cnt;
   return HO_OK;
 }
 

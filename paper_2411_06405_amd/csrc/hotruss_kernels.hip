@@ -1093,4 +1093,70 @@ __global__ void k_init_rows(Dev d) {
     d.len[x] = d.rp[x + 1] - d.rp[x];
 }
 
+// ============================================ (k,h)-truss extraction
+// The (k,h)-truss is the edge set {e : t(e,h) >= k} (Def. 4: t(e,h) is the
+// largest k whose truss holds e, and trusses are nested).  Its connected
+// components come from a lock-free union-find over the vertices: a root is
+// only ever linked below a smaller root, so parent[x] <= x throughout and
+// every component's root is its smallest vertex.
+
+__device__ __forceinline__ uint32_t cc_find(uint32_t* parent, uint32_t x) {
+  uint32_t p = parent[x];
+  while (p != x) {
+    const uint32_t g = parent[p];
+    if (g != p) parent[x] = g;  // path halving (any ancestor is a valid parent)
+    x = p;
+    p = g;
+  }
+  return x;
+}
+
+__global__ void k_cc_init(uint32_t* __restrict__ parent, uint32_t* __restrict__ touched,
+                          uint32_t n) {
+  for (uint32_t x = blockIdx.x * blockDim.x + threadIdx.x; x < n; x += gridDim.x * blockDim.x) {
+    parent[x] = x;
+    touched[x] = 0;
+  }
+}
+
+__global__ void k_cc_hook(Dev d, const uint32_t* __restrict__ t, uint32_t k,
+                          uint32_t* parent, uint32_t* __restrict__ touched) {
+  if (d.ctl->err) return;
+  for (uint32_t e = blockIdx.x * blockDim.x + threadIdx.x; e < d.m; e += gridDim.x * blockDim.x) {
+    if (t[e] < k) continue;
+    const uint32_t u = d.eu[e], v = d.ev[e];
+    touched[u] = 1;
+    touched[v] = 1;
+    while (true) {
+      uint32_t ru = cc_find(parent, u), rv = cc_find(parent, v);
+      if (ru == rv) break;
+      if (ru > rv) {
+        const uint32_t tmp = ru;
+        ru = rv;
+        rv = tmp;
+      }
+      // link the larger root below the smaller one, if it is still a root
+      if (atomicCAS(&parent[rv], rv, ru) == rv) break;
+    }
+  }
+}
+
+// Every vertex points at its root; edges of the truss take their component's
+// root, the others UINT32_MAX; roots of touched vertices are counted.
+__global__ void k_cc_label(Dev d, const uint32_t* __restrict__ t, uint32_t k, uint32_t* parent,
+                           const uint32_t* __restrict__ touched, uint32_t* __restrict__ out,
+                           uint32_t* __restrict__ count) {
+  if (d.ctl->err) return;
+  const uint32_t stride = gridDim.x * blockDim.x;
+  for (uint32_t base = blockIdx.x * blockDim.x + (threadIdx.x & ~(WAVE - 1)); base < d.n;
+       base += stride) {
+    const uint32_t x = base + lane_id();
+    const bool root = x < d.n && touched[x] && parent[x] == x;
+    const uint32_t c = (uint32_t)__popcll(__ballot(root));
+    if (lane_id() == 0 && c) atomicAdd(count, c);
+  }
+  for (uint32_t e = blockIdx.x * blockDim.x + threadIdx.x; e < d.m; e += stride)
+    out[e] = t[e] >= k ? cc_find(parent, d.eu[e]) : 0xffffffffu;
+}
+
 }  // namespace hotruss
