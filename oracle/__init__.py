@@ -9,7 +9,9 @@ from .oracle import (OracleError, build, certify, decompose, h_support, h_suppor
                      lib_path)
 from .brute import brute_trussness, brute_h_support
 from .components import truss_components
+from .hindex import hindex_sequence, hindex_trussness
 
 __all__ = ["OracleError", "build", "certify", "decompose", "h_support", "h_support_edges",
            "lib_path",
-           "brute_trussness", "brute_h_support", "truss_components"]
+           "brute_trussness", "brute_h_support", "truss_components",
+           "hindex_sequence", "hindex_trussness"]
