@@ -227,6 +227,47 @@ hoStatus hoTrussComponents(const uint32_t *row_ptr, const uint32_t *col_idx, uin
                            uint32_t *out_count, void *workspace, size_t workspace_bytes,
                            hipStream_t stream);
 
+/* ------------------------------------------------------------------------
+ * H-index fixpoint method (Section 4: the h-hop reachable path key, the
+ * higher-order H-index, Theorems 1-2; Section 4.2, Algorithm 2, the parallel
+ * update loop, and the asynchronous updating of Section 4.1).  A second exact
+ * algorithm for the same trussness: starting from H(e) = sup_G(e, h), every
+ * sweep sets
+ *     H(u,v) = H-index of { min(P(u,w), P(v,w)) : w a common h-hop neighbour }
+ * where P(x,w) is the largest smallest-H over paths of at most h edges from x
+ * to w; the values never rise and stop at t(e, h) - 2.
+ *
+ *   flags       0: synchronous sweeps (every update reads the previous
+ *               sweep's values; the sequence of the paper's definition).
+ *               HO_HINDEX_ASYNC: asynchronous sweeps (vertices in 8 chunks
+ *               taken in order; a chunk reads the values earlier chunks of
+ *               the same sweep wrote).  HO_HINDEX_ALL: recompute every path-key
+ *               row and edge in every sweep instead of only those whose inputs
+ *               changed (same values; for measurement).
+ *   max_sweeps  0: run until a sweep changes nothing (that sweep is counted);
+ *               else stop after that many sweeps.  out_trussness then holds
+ *               H + 2 of the last sweep (synchronous: H^(max_sweeps) + 2).
+ *   out_trussness  device [m]: H + 2 per canonical edge id.
+ *   out_sweeps  host: sweeps run.
+ *   workspace   device, caller-owned.  Its size depends on the total size of
+ *               the h-hop balls, known only on the device: pass at least
+ *               hoTrussHIndexWorkspaceBytes(n, m, h) bytes; when the balls
+ *               need more, the call returns HO_ERR_WORKSPACE with
+ *               *needed_bytes set (4 bytes per ball member, twice for h >= 3,
+ *               on top of the minimum); call again with that much.  On success
+ *               *needed_bytes (if not NULL) is the size this graph needed.
+ *   Errors as for hoTrussDecompose; flags outside the two bits give
+ *   HO_ERR_INVALID_ARG.  hoTrussLastStats afterwards: rounds = sweeps, events =
+ *   value changes, work[0] = edge evaluations, work[1] = path-key rows built,
+ *   device_ms = the whole call. */
+#define HO_HINDEX_ASYNC 0x1u
+#define HO_HINDEX_ALL 0x2u
+size_t hoTrussHIndexWorkspaceBytes(uint32_t n, uint64_t m, uint32_t h);
+hoStatus hoTrussHIndex(const uint32_t *row_ptr, const uint32_t *col_idx, uint32_t n, uint64_t m,
+                       uint32_t h, uint32_t flags, uint32_t max_sweeps, uint32_t *out_trussness,
+                       uint32_t *out_sweeps, void *workspace, size_t workspace_bytes,
+                       size_t *needed_bytes, hipStream_t stream);
+
 const char *hoStatusString(hoStatus s);
 
 #ifdef __cplusplus

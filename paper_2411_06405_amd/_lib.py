@@ -16,6 +16,7 @@ import torch
 LIB_PATH = Path(__file__).resolve().parent / "libhotruss.so"
 
 HO_OK = 0
+HO_ERR_WORKSPACE = -3
 STATUS = {0: "HO_OK", -1: "HO_ERR_INVALID_ARG", -2: "HO_ERR_BAD_CSR", -3: "HO_ERR_WORKSPACE",
           -4: "HO_ERR_HIP", -5: "HO_ERR_BUDGET", -6: "HO_ERR_CANCELLED", -7: "HO_ERR_BUSY",
           -8: "HO_ERR_NOT_FOUND", -9: "HO_ERR_INTERNAL"}
@@ -85,6 +86,11 @@ def _declare(lib):
     lib.hoTrussComponents.argtypes = [vp, vp, u32, u64, vp, u32, vp, C.POINTER(u32), vp, sz, vp]
     lib.hoTrussComponents.restype = C.c_int
     lib.hoSessionDestroy.restype = C.c_int
+    lib.hoTrussHIndexWorkspaceBytes.argtypes = [u32, u64, u32]
+    lib.hoTrussHIndexWorkspaceBytes.restype = sz
+    lib.hoTrussHIndex.argtypes = [vp, vp, u32, u64, u32, u32, u32, vp, C.POINTER(u32), vp, sz,
+                                  C.POINTER(sz), vp]
+    lib.hoTrussHIndex.restype = C.c_int
     return lib
 
 
@@ -100,7 +106,11 @@ lib = load()
 EXPORTS = ["hoStatusString", "hoTrussWorkspaceBytes", "hoTrussHSupport", "hoTrussDecompose",
            "hoTrussLastStats", "hoTrussBatchedWorkspaceBytes", "hoTrussDecomposeBatched",
            "hoSessionCreate", "hoSubmit", "hoSessionProgress", "hoPoll", "hoCancel",
-           "hoSessionDestroy", "hoTrussComponentsWorkspaceBytes", "hoTrussComponents"]
+           "hoSessionDestroy", "hoTrussComponentsWorkspaceBytes", "hoTrussComponents",
+           "hoTrussHIndexWorkspaceBytes", "hoTrussHIndex"]
+
+HO_HINDEX_ASYNC = 0x1
+HO_HINDEX_ALL = 0x2
 
 
 def _check(rc: int, what: str):
@@ -194,6 +204,43 @@ def decompose_graph(g, h: int, **kw):
 
 def h_support_graph(g, h: int, **kw) -> np.ndarray:
     return to_numpy_u32(h_support(g.row_ptr, g.col_idx, g.n, h, **kw))
+
+
+def hindex(row_ptr, col_idx, n: int, h: int, asynchronous: bool = False, track: bool = True,
+           max_sweeps: int = 0, workspace=None, stream=None, device="cuda"):
+    """Trussness by the H-index fixpoint method: (t device tensor, sweeps).
+
+    The workspace size depends on the h-hop balls, which only the device
+    knows: a first call with the minimum reports the size needed; the
+    workspace is then grown and the call repeated.  A caller-given workspace
+    that is too small raises."""
+    rp = _dev_u32(row_ptr, device)
+    ci = _dev_u32(col_idx, device)
+    m = ci.numel() // 2
+    out = torch.empty(max(m, 1), dtype=torch.int32, device=device)
+    flags = (HO_HINDEX_ASYNC if asynchronous else 0) | (0 if track else HO_HINDEX_ALL)
+    sweeps = C.c_uint32()
+    needed = C.c_size_t()
+    grow = workspace is None
+    if grow:
+        nb = int(lib.hoTrussHIndexWorkspaceBytes(n, m, h))
+        workspace = torch.empty(max(nb, 1), dtype=torch.uint8, device=device)
+    for _ in range(2):
+        rc = lib.hoTrussHIndex(rp.data_ptr(), ci.data_ptr(), n, m, h, flags, int(max_sweeps),
+                               out.data_ptr(), C.byref(sweeps), workspace.data_ptr(),
+                               workspace.numel(), C.byref(needed), _stream(stream))
+        if rc == HO_ERR_WORKSPACE and grow and needed.value > workspace.numel():
+            workspace = torch.empty(int(needed.value), dtype=torch.uint8, device=device)
+            continue
+        break
+    _check(rc, "hoTrussHIndex")
+    return out[:m], int(sweeps.value)
+
+
+def hindex_graph(g, h: int, **kw):
+    """Convenience for host graphs: numpy trussness and the sweep count."""
+    t, sweeps = hindex(g.row_ptr, g.col_idx, g.n, h, **kw)
+    return to_numpy_u32(t), sweeps
 
 
 def truss_components(row_ptr, col_idx, n: int, trussness, k: int, workspace=None, stream=None,

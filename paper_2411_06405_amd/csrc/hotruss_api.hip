@@ -15,6 +15,7 @@
 #include "../../include/hotruss.h"
 #include "hotruss_dev.h"
 #include "hotruss_kernels.hip"
+#include "hotruss_hindex.hip"
 
 // status words per engine slot: {done, halt, live edges, unused}
 #define HO_STATUS_WORDS 4
@@ -942,6 +943,41 @@ hoStatus check_common(const uint32_t* rp, const uint32_t* ci, uint32_t n, uint64
   return HO_OK;
 }
 
+// ---------------------------------------------------- H-index fixpoint
+constexpr uint32_t HX_CHUNKS = 8;  // vertex chunks of an asynchronous sweep
+
+// Workspace of the H-index method: the support-only plan (balls of G, edge
+// ids, H in `sup`), then the method's own arrays; the path keys follow at
+// `base` and take one (h <= 2) or two (h >= 3) u32 per ball member.
+struct HxPlan {
+  Plan p;
+  size_t off_wp, off_cnt, off_boff, off_dirty, off_touched, off_tbits, off_tlist, off_ord,
+      off_cbound, off_ctr, base;
+};
+
+bool make_hx_plan(uint32_t n, uint64_t m, uint32_t h, HxPlan* out) {
+  HxPlan q;
+  if (!make_plan(n, m, h, nullptr, false, &q.p)) return false;
+  size_t o = q.p.total - ALIGN;
+  auto take = [&](size_t bytes) { size_t r = o; o += up(bytes); return r; };
+  const size_t W = q.p.W;
+  q.off_wp = take(4 * W * n);
+  q.off_cnt = take(4 * (size_t)n + 4);
+  q.off_boff = take(8 * ((size_t)n + 1));
+  q.off_dirty = take(4 * (size_t)n + 4);
+  q.off_touched = take(4 * (size_t)n + 4);
+  q.off_tbits = take(8 * W);
+  q.off_tlist = take(4 * W);
+  q.off_ord = take(4 * m + 4);
+  q.off_cbound = take(4 * (HX_CHUNKS + 1));
+  q.off_ctr = take(64);
+  q.base = o;
+  *out = q;
+  return true;
+}
+
+size_t hx_key_bytes(uint64_t members) { return up(4 * members + 4); }
+
 }  // namespace
 }  // namespace hotruss
 
@@ -1301,6 +1337,127 @@ hoStatus hoTrussComponents(const uint32_t* row_ptr, const uint32_t* col_idx, uin
   HIPCHK(hipMemcpyAsync(&cnt, counter, sizeof(uint32_t), hipMemcpyDeviceToHost, stream));
   HIPCHK(hipStreamSynchronize(stream));
   *out_count = cnt;
+  return HO_OK;
+}
+
+
+// ------------------------------------------------------ H-index fixpoint
+size_t hoTrussHIndexWorkspaceBytes(uint32_t n, uint64_t m, uint32_t h) {
+  HxPlan q;
+  if (!make_hx_plan(n, m, h, &q)) return 0;
+  return q.base + ALIGN;
+}
+
+hoStatus hoTrussHIndex(const uint32_t* row_ptr, const uint32_t* col_idx, uint32_t n, uint64_t m,
+                       uint32_t h, uint32_t flags, uint32_t max_sweeps, uint32_t* out_trussness,
+                       uint32_t* out_sweeps, void* workspace, size_t workspace_bytes,
+                       size_t* needed_bytes, hipStream_t stream) {
+  if (!out_sweeps || (flags & ~(HO_HINDEX_ASYNC | HO_HINDEX_ALL))) return HO_ERR_INVALID_ARG;
+  hoStatus st = check_common(row_ptr, col_idx, n, m, h, out_trussness, workspace);
+  if (st != HO_OK) return st;
+  t_stats = hoStats{};
+  if (m == 0) {
+    *out_sweeps = 0;
+    if (needed_bytes) *needed_bytes = 0;
+    return HO_OK;
+  }
+  HxPlan q;
+  if (!make_hx_plan(n, m, h, &q)) return HO_ERR_INVALID_ARG;
+  if (needed_bytes) *needed_bytes = q.base + ALIGN;
+  if (workspace_bytes < q.base + ALIGN) return HO_ERR_WORKSPACE;
+  Dev d = carve(q.p, workspace, row_ptr, col_idx, nullptr, nullptr);
+  const uintptr_t wsb = ((uintptr_t)workspace + ALIGN - 1) / ALIGN * ALIGN;
+  auto at = [&](size_t off) { return (void*)(wsb + off); };
+  EventGuard ev0, ev1;
+  HIPCHK(hipEventCreate(&ev0.e));
+  HIPCHK(hipEventCreate(&ev1.e));
+  HIPCHK(hipEventRecord(ev0.e, stream));
+  // G's balls and H^(0) = sup_G(e, h)
+  HOCHK(run_init(d, d.sup, nullptr, stream));
+  Ctl c;
+  HOCHK(read_ctl(d, &c, stream));
+  if (c.err) return HO_ERR_BAD_CSR;
+  Hx x;
+  memset(&x, 0, sizeof x);
+  x.rp = d.rp; x.ci = d.ci; x.eid = d.eid; x.eu = d.eu; x.ev = d.ev;
+  x.up_cnt = d.up_cnt; x.up_off = d.up_off;
+  for (uint32_t j = 1; j <= d.h; ++j) x.L[j] = d.L[j];
+  x.n = d.n; x.m = d.m; x.h = d.h; x.W = d.W;
+  x.wp = (uint32_t*)at(q.off_wp);
+  x.cnt = (uint32_t*)at(q.off_cnt);
+  x.boff = (uint64_t*)at(q.off_boff);
+  x.H = d.sup;
+  x.dirty = (uint32_t*)at(q.off_dirty);
+  x.touched = (uint32_t*)at(q.off_touched);
+  x.tbits = (uint64_t*)at(q.off_tbits);
+  x.tlist = (uint32_t*)at(q.off_tlist);
+  x.ord = (uint32_t*)at(q.off_ord);
+  x.cbound = (uint32_t*)at(q.off_cbound);
+  x.ctr = (uint32_t*)at(q.off_ctr);
+  const unsigned T = 256;
+  hipLaunchKernelGGL(k_hx_rank, dim3(grid_for(n, T / WAVE)), dim3(T), 0, stream, x);
+  hipLaunchKernelGGL(k_hx_scan, dim3(1), dim3(1024), 0, stream, x.cnt, x.boff, n);
+  uint64_t members = 0;
+  HIPCHK(hipMemcpyAsync(&members, x.boff + n, sizeof members, hipMemcpyDeviceToHost, stream));
+  HIPCHK(hipStreamSynchronize(stream));
+  const uint32_t nbuf = d.h >= 3 ? 2 : 1;
+  const size_t need = q.base + nbuf * hx_key_bytes(members) + ALIGN;
+  if (needed_bytes) *needed_bytes = need;
+  if (workspace_bytes < need) return HO_ERR_WORKSPACE;
+  x.P[0] = (uint32_t*)at(q.base);
+  x.P[1] = nbuf == 2 ? (uint32_t*)at(q.base + hx_key_bytes(members)) : nullptr;
+  const bool async = flags & HO_HINDEX_ASYNC;
+  x.track = (flags & HO_HINDEX_ALL) ? 0u : 1u;
+  const uint32_t chunks = async ? HX_CHUNKS : 1;
+  if (async) {
+    hipLaunchKernelGGL(k_hx_order, dim3(grid_for(n, T / WAVE)), dim3(T), 0, stream, x);
+    hipLaunchKernelGGL(k_hx_bounds, dim3(1), dim3(64), 0, stream, x, chunks);
+  }
+  hipLaunchKernelGGL(k_fill32, dim3(grid_for(n, T)), dim3(T), 0, stream, x.dirty, (size_t)n, 1u);
+  hipLaunchKernelGGL(k_fill32, dim3(grid_for(n, T)), dim3(T), 0, stream, x.touched, (size_t)n, 0u);
+  HIPCHK(hipGetLastError());
+  uint32_t sweeps = 0;
+  uint64_t evals = 0, rows = 0, changes = 0;
+  while (true) {
+    hipLaunchKernelGGL(k_fill32, dim3(1), dim3(64), 0, stream, x.ctr, (size_t)4, 0u);
+    for (uint32_t cc = 0; cc < chunks; ++cc) {
+      const uint32_t vlo = (uint32_t)((uint64_t)cc * n / chunks);
+      const uint32_t vhi = (uint32_t)((uint64_t)(cc + 1) * n / chunks);
+      if (vhi > vlo)
+        hipLaunchKernelGGL(k_hx_paths, dim3(grid_for(vhi - vlo, 1)), dim3(T), 0, stream, x, vlo,
+                           vhi);
+      hipLaunchKernelGGL(k_hx_edges, dim3(grid_for((m + chunks - 1) / chunks, T / WAVE)),
+                         dim3(T), 0, stream, x, cc, async ? 1u : 0u);
+    }
+    if (x.track) {
+      hipLaunchKernelGGL(k_hx_tbits, dim3(grid_for(x.W, T)), dim3(T), 0, stream, x);
+      hipLaunchKernelGGL(k_hx_dirty, dim3(grid_for(n, T / WAVE)), dim3(T), 0, stream, x);
+    }
+    HIPCHK(hipGetLastError());
+    uint32_t hc[4];
+    HIPCHK(hipMemcpyAsync(hc, x.ctr, sizeof hc, hipMemcpyDeviceToHost, stream));
+    HIPCHK(hipStreamSynchronize(stream));
+    ++sweeps;
+    changes += hc[HX_CTR_CHANGED];
+    evals += hc[HX_CTR_EVALS];
+    rows += hc[HX_CTR_ROWS];
+    if (hc[HX_CTR_CHANGED] == 0 || (max_sweeps && sweeps >= max_sweeps)) break;
+    // every sweep but the last lowers the sum of H, which starts below m*n
+    if (sweeps > m * (uint64_t)n + 1) return HO_ERR_INTERNAL;
+  }
+  hipLaunchKernelGGL(k_hx_finish, dim3(grid_for(m, T)), dim3(T), 0, stream, x.H, out_trussness,
+                     d.m);
+  HIPCHK(hipGetLastError());
+  HIPCHK(hipEventRecord(ev1.e, stream));
+  HIPCHK(hipEventSynchronize(ev1.e));
+  float ms = 0.f;
+  HIPCHK(hipEventElapsedTime(&ms, ev0.e, ev1.e));
+  t_stats.rounds = sweeps;
+  t_stats.events = changes;
+  t_stats.device_ms = ms;
+  t_stats.work[0] = evals;
+  t_stats.work[1] = rows;
+  *out_sweeps = sweeps;
   return HO_OK;
 }
 

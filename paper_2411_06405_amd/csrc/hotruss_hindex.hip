@@ -1,0 +1,389 @@
+// hotruss_hindex.hip -- CDNA4 (gfx950) kernels of the H-index fixpoint
+// method for higher-order truss decomposition (paper, Section 4.1: the h-hop
+// reachable path key and the higher-order H-index; Section 4.2, Algorithm 2:
+// the parallel update loop; Section 4.1: asynchronous updating).
+//
+// Every sweep recomputes, for each edge e = (u,v),
+//     H(e) <- H({ min(P(u,w), P(v,w)) : w in the common h-hop neighbourhood }),
+// where P(x,w) is the largest smallest-key over paths of at most h edges
+// from x to w, keys being the current H values.  The values never rise
+// (Theorem 1) and settle at t(e,h) - 2 (Theorem 2).
+//
+// Path keys depend on the source vertex only, so a sweep first builds the
+// path-key row of every vertex that needs one (k_hx_paths) and then updates
+// the edges (k_hx_edges), instead of the paper's per-edge searches.
+//
+// Layout.  L[h](x) is the closed h-hop ball of x in G as a dense bitset row
+// (built once by the peeling method's ball kernels; G never changes here).
+// Row x of the path keys holds one u32 per member of L[h](x), in increasing
+// vertex order: the key of w is at P[boff[x] + rank_x(w)], with
+//     rank_x(w) = wp[x*W + w/64] + popcount(L[h](x) word w/64 below bit w),
+// wp holding, per row and word, the members in the row's earlier words.
+// A key of 0 also stands for "not reached yet": a path key is never below
+// 0, so the placeholder can only lose a maximum.
+//
+// Change tracking (exact; the same answer as recomputing everything): an edge
+// whose H changed marks both endpoints "touched".  P(x,.) reads only keys of
+// edges with an endpoint within h-1 hops of x, so a row needs rebuilding only
+// if L[h-1](x) (for h = 1: x itself) holds a touched vertex; an edge needs
+// re-evaluation only if one of its endpoints' rows was rebuilt.
+//
+// Asynchronous sweeps split the vertices into consecutive chunks processed in
+// order; chunk c rebuilds its rows from the keys as they stand (including the
+// ones earlier chunks of the same sweep changed) and then updates the edges
+// whose upper endpoint lies in c, so both endpoint rows are from this sweep.
+#include "hotruss_dev.h"
+
+namespace hotruss {
+
+constexpr uint32_t HX_SRC = 1024;   // relaxation sources staged per batch
+constexpr uint32_t HX_STAGE_WORDS = HX_SRC / 64;
+constexpr uint32_t HX_CTR_CHANGED = 0, HX_CTR_EVALS = 1, HX_CTR_ROWS = 2, HX_CTR_TLIST = 3;
+
+struct Hx {
+  const uint32_t* rp;      // row_ptr [n+1]
+  const uint32_t* ci;      // col_idx [2m]
+  const uint32_t* eid;     // slot -> edge id [2m]
+  const uint32_t* eu;      // edge -> lower endpoint [m]
+  const uint32_t* ev;      // edge -> upper endpoint [m]
+  const uint32_t* up_cnt;  // per row: neighbours above the row vertex [n]
+  const uint32_t* up_off;  // exclusive prefix sum of up_cnt [n]
+  const uint64_t* L[HMAX + 1];  // closed balls of G, n rows of W words
+  uint32_t n, m, h, W;
+  uint32_t* wp;        // per row and word: members of L[h] in earlier words [n*W]
+  uint32_t* cnt;       // |L[h](x)| [n]
+  uint64_t* boff;      // start of row x's path keys [n+1]
+  uint32_t* H;         // current H-index of every edge [m]
+  uint32_t* P[2];      // path keys; P[0] holds the finished rows (P[1]: h >= 3 only)
+  uint32_t* dirty;     // row x is rebuilt (and its edges re-evaluated) this sweep [n]
+  uint32_t* touched;   // x is an endpoint of an edge changed this sweep [n]
+  uint64_t* tbits;     // touched as a bitset [W]
+  uint32_t* tlist;     // nonzero words of tbits [W]
+  uint32_t* ord;       // edge ids ordered by upper endpoint [m]
+  uint32_t* cbound;    // chunk c's edges are ord[cbound[c] .. cbound[c+1]) [chunks+1]
+  uint32_t* ctr;       // counters: changed, evaluated, rows built, tlist length
+  uint32_t track;      // change tracking on: skip clean rows and edges
+};
+
+__device__ __forceinline__ uint32_t hx_rank(const Hx& x, uint32_t u, uint32_t w) {
+  const size_t i = (size_t)u * x.W + (w >> 6);
+  const uint64_t below = (1ull << (w & 63)) - 1;
+  return x.wp[i] + (uint32_t)__popcll(x.L[x.h][i] & below);
+}
+
+// Ball sizes and per-word member counts of every row (one wave per row).
+__global__ void __launch_bounds__(256) k_hx_rank(Hx x) {
+  const uint32_t lane = lane_id(), wpb = blockDim.x / WAVE;
+  const uint64_t* Lh = x.L[x.h];
+  for (uint32_t r = blockIdx.x * wpb + threadIdx.x / WAVE; r < x.n; r += gridDim.x * wpb) {
+    uint32_t run = 0;
+    for (uint32_t i0 = 0; i0 < x.W; i0 += WAVE) {
+      const uint32_t i = i0 + lane;
+      const uint32_t c = i < x.W ? (uint32_t)__popcll(Lh[(size_t)r * x.W + i]) : 0;
+      uint32_t tot;
+      const uint32_t ex = wave_excl_scan(c, &tot);
+      if (i < x.W) x.wp[(size_t)r * x.W + i] = run + ex;
+      run += tot;
+    }
+    if (lane == 0) x.cnt[r] = run;
+  }
+}
+
+// 64-bit exclusive prefix sum of cnt[0..n) into off[0..n]; one workgroup of
+// 1024 threads, each summing a contiguous segment.
+__global__ void __launch_bounds__(1024) k_hx_scan(const uint32_t* __restrict__ cnt,
+                                                   uint64_t* __restrict__ off, uint32_t n) {
+  __shared__ uint64_t s[1024];
+  const uint32_t t = threadIdx.x, per = (n + 1023) / 1024;
+  const uint32_t b = min(n, t * per), e = min(n, b + per);
+  uint64_t sum = 0;
+  for (uint32_t i = b; i < e; ++i) sum += cnt[i];
+  s[t] = sum;
+  __syncthreads();
+  for (uint32_t o = 1; o < 1024; o <<= 1) {
+    const uint64_t v = t >= o ? s[t - o] : 0;
+    __syncthreads();
+    s[t] += v;
+    __syncthreads();
+  }
+  uint64_t run = s[t] - sum;
+  for (uint32_t i = b; i < e; ++i) {
+    off[i] = run;
+    run += cnt[i];
+  }
+  if (t == 1023) off[n] = s[1023];
+}
+
+// Edge ids in order of their upper endpoint: row x's lower slots (its first
+// deg(x) - up_cnt(x) slots) list the edges whose upper endpoint is x, and the
+// lower slots of rows before x number rp[x] - up_off[x].
+__global__ void __launch_bounds__(256) k_hx_order(Hx x) {
+  const uint32_t lane = lane_id(), wpb = blockDim.x / WAVE;
+  for (uint32_t r = blockIdx.x * wpb + threadIdx.x / WAVE; r < x.n; r += gridDim.x * wpb) {
+    const uint32_t beg = x.rp[r], nlow = x.rp[r + 1] - beg - x.up_cnt[r];
+    const uint32_t at = beg - x.up_off[r];
+    for (uint32_t j = lane; j < nlow; j += WAVE) x.ord[at + j] = x.eid[beg + j];
+  }
+}
+
+// Chunk c covers vertices [c*n/chunks, (c+1)*n/chunks).
+__global__ void k_hx_bounds(Hx x, uint32_t chunks) {
+  const uint32_t c = blockIdx.x * blockDim.x + threadIdx.x;
+  if (c > chunks) return;
+  const uint32_t v = (uint32_t)((uint64_t)c * x.n / chunks);
+  x.cbound[c] = v < x.n ? x.rp[v] - x.up_off[v] : x.m;
+}
+
+// Relax the staged sources s_y[0..nb) with path keys s_k into row `dst` of
+// vertex u: for every edge (y, w), w != u, key(u,w) >= min(s_k, H(y,w)).
+// Work is spread over the whole workgroup by a prefix sum of the sources'
+// degrees (sources with key 0 contribute nothing and get degree 0).
+__device__ void hx_relax(const Hx& x, uint32_t u, uint32_t nb, uint32_t* __restrict__ dst,
+                         const uint32_t* s_y, const uint32_t* s_k, uint32_t* s_pre) {
+  if (threadIdx.x < WAVE) {
+    uint32_t run = 0;
+    for (uint32_t i0 = 0; i0 < nb; i0 += WAVE) {
+      const uint32_t i = i0 + threadIdx.x;
+      uint32_t d = 0;
+      if (i < nb && s_k[i]) d = x.rp[s_y[i] + 1] - x.rp[s_y[i]];
+      uint32_t tot;
+      const uint32_t ex = wave_excl_scan(d, &tot);
+      if (i < nb) s_pre[i] = run + ex;
+      run += tot;
+    }
+    if (threadIdx.x == 0) s_pre[nb] = run;
+  }
+  __syncthreads();
+  const uint32_t total = s_pre[nb];
+  for (uint32_t k = threadIdx.x; k < total; k += blockDim.x) {
+    // the last source whose range starts at or before k
+    uint32_t lo = 0, hi = nb;
+    while (hi - lo > 1) {
+      const uint32_t mid = (lo + hi) >> 1;
+      if (s_pre[mid] <= k) lo = mid; else hi = mid;
+    }
+    const uint32_t y = s_y[lo];
+    const uint32_t r = x.rp[y] + (k - s_pre[lo]);
+    const uint32_t w = x.ci[r];
+    if (w == u) continue;
+    const uint32_t val = min(s_k[lo], x.H[x.eid[r]]);
+    if (val) atomicMax(&dst[hx_rank(x, u, w)], val);
+  }
+}
+
+// Path-key rows of the vertices in [vlo, vhi) (one workgroup per vertex):
+// one hop from u's own edges, a second hop relaxed in place (its sources read
+// the direct keys from H, never the row), further hops double-buffered so a
+// pass extends paths by exactly one edge.
+__global__ void __launch_bounds__(256) k_hx_paths(Hx x, uint32_t vlo, uint32_t vhi) {
+  __shared__ uint32_t s_y[HX_SRC], s_k[HX_SRC], s_pre[HX_SRC + 1];
+  __shared__ uint32_t s_cnt[HX_STAGE_WORDS];
+  uint32_t built = 0;
+  for (uint32_t u = vlo + blockIdx.x; u < vhi; u += gridDim.x) {
+    if (x.track && !x.dirty[u]) continue;
+    ++built;
+    const uint64_t base = x.boff[u];
+    const uint32_t len = (uint32_t)(x.boff[u + 1] - base);
+    uint32_t cur = x.h >= 2 ? ((x.h - 2) & 1u) : 0u;  // so that the last hop lands in P[0]
+    uint32_t* row = x.P[cur] + base;
+    for (uint32_t i = threadIdx.x; i < len; i += blockDim.x) row[i] = 0;
+    __syncthreads();
+    const uint32_t beg = x.rp[u], end = x.rp[u + 1];
+    for (uint32_t q = beg + threadIdx.x; q < end; q += blockDim.x)
+      row[hx_rank(x, u, x.ci[q])] = x.H[x.eid[q]];
+    __syncthreads();
+    if (x.h >= 2) {
+      for (uint32_t q0 = beg; q0 < end; q0 += HX_SRC) {
+        const uint32_t nb = min(HX_SRC, end - q0);
+        for (uint32_t i = threadIdx.x; i < nb; i += blockDim.x) {
+          s_y[i] = x.ci[q0 + i];
+          s_k[i] = x.H[x.eid[q0 + i]];
+        }
+        __syncthreads();
+        hx_relax(x, u, nb, row, s_y, s_k, s_pre);
+        __syncthreads();
+      }
+    }
+    for (uint32_t j = 3; j <= x.h; ++j) {
+      const uint32_t* src = x.P[cur] + base;
+      uint32_t* dst = x.P[cur ^ 1u] + base;
+      for (uint32_t i = threadIdx.x; i < len; i += blockDim.x) dst[i] = src[i];
+      __syncthreads();
+      // sources: members y != u of L[j-1](u), HX_STAGE_WORDS words at a time
+      const uint64_t* Lp = x.L[j - 1] + (size_t)u * x.W;
+      const uint64_t* Lh = x.L[x.h] + (size_t)u * x.W;
+      for (uint32_t i0 = 0; i0 < x.W; i0 += HX_STAGE_WORDS) {
+        const uint32_t i = i0 + threadIdx.x;
+        uint64_t bits = 0;
+        if (threadIdx.x < HX_STAGE_WORDS && i < x.W) {
+          bits = Lp[i];
+          if (i == (u >> 6)) bits &= ~(1ull << (u & 63));
+        }
+        if (threadIdx.x < HX_STAGE_WORDS) s_cnt[threadIdx.x] = (uint32_t)__popcll(bits);
+        __syncthreads();
+        uint32_t at = 0, nb = 0;
+        for (uint32_t t = 0; t < HX_STAGE_WORDS; ++t) {
+          if (t == threadIdx.x) at = nb;
+          nb += s_cnt[t];
+        }
+        if (threadIdx.x < HX_STAGE_WORDS && bits) {
+          const uint64_t hw = Lh[i];
+          const uint32_t rb = x.wp[(size_t)u * x.W + i];
+          uint64_t b = bits;
+          do {
+            const uint32_t bit = (uint32_t)__ffsll((long long)b) - 1;
+            const uint32_t y = i * 64 + bit;
+            s_y[at] = y;
+            s_k[at] = src[rb + (uint32_t)__popcll(hw & ((1ull << bit) - 1))];
+            ++at;
+            b &= b - 1;
+          } while (b);
+        }
+        __syncthreads();
+        if (nb) hx_relax(x, u, nb, dst, s_y, s_k, s_pre);
+        __syncthreads();
+      }
+      cur ^= 1u;
+    }
+  }
+  if (threadIdx.x == 0 && built) atomicAdd(&x.ctr[HX_CTR_ROWS], built);
+}
+
+// f(min(P(u,w), P(v,w))) for every common member w != u, v of the two balls
+// (all 64 lanes call; each lane takes every 64th word).
+template <class F>
+__device__ __forceinline__ void hx_common(const Hx& x, uint32_t u, uint32_t v, F&& f) {
+  const uint64_t* Lu = x.L[x.h] + (size_t)u * x.W;
+  const uint64_t* Lv = x.L[x.h] + (size_t)v * x.W;
+  const uint32_t* Wu = x.wp + (size_t)u * x.W;
+  const uint32_t* Wv = x.wp + (size_t)v * x.W;
+  const uint32_t* Pu = x.P[0] + x.boff[u];
+  const uint32_t* Pv = x.P[0] + x.boff[v];
+  for (uint32_t i = lane_id(); i < x.W; i += WAVE) {
+    const uint64_t a = Lu[i], b = Lv[i];
+    uint64_t c = a & b;
+    if (i == (u >> 6)) c &= ~(1ull << (u & 63));
+    if (i == (v >> 6)) c &= ~(1ull << (v & 63));
+    if (!c) continue;
+    const uint32_t ra = Wu[i], rb = Wv[i];
+    do {
+      const uint64_t below = (c & (~c + 1)) - 1;  // bits under the lowest set bit
+      f(min(Pu[ra + (uint32_t)__popcll(a & below)], Pv[rb + (uint32_t)__popcll(b & below)]));
+      c &= c - 1;
+    } while (c);
+  }
+}
+
+// Update the edges of chunk `chunk` (ord[cbound[chunk] .. cbound[chunk+1]))
+// or, when ord is not used, every edge; one wave per edge.  The new value is the largest y <= H(e)
+// with at least y common members keyed >= y: one pass counts the members
+// keyed >= H(e) (enough when H(e) stands); otherwise passes with a 64-bin
+// histogram narrow [lo, hi) by 64x each until one value is left.
+__global__ void __launch_bounds__(256) k_hx_edges(Hx x, uint32_t chunk, uint32_t use_ord) {
+  __shared__ uint32_t s_hist[256 / WAVE][WAVE];
+  const uint32_t lane = lane_id(), wv = threadIdx.x / WAVE, wpb = blockDim.x / WAVE;
+  uint32_t* hist = s_hist[wv];
+  uint32_t evals = 0, changes = 0;
+  const uint32_t klo = use_ord ? x.cbound[chunk] : 0, khi = use_ord ? x.cbound[chunk + 1] : x.m;
+  for (uint32_t k = klo + blockIdx.x * wpb + wv; k < khi; k += gridDim.x * wpb) {
+    const uint32_t e = use_ord ? x.ord[k] : k;
+    const uint32_t u = x.eu[e], v = x.ev[e];
+    if (x.track && !x.dirty[u] && !x.dirty[v]) continue;
+    const uint32_t c = x.H[e];
+    if (c == 0) continue;
+    ++evals;
+    uint32_t ge = 0;
+    hx_common(x, u, v, [&](uint32_t val) { ge += val >= c; });
+    ge = wave_sum(ge);
+    if (ge >= c) continue;
+    // invariant: lo is feasible, hi is not, above = members keyed >= hi
+    uint32_t lo = 0, hi = c, above = ge, y = 0;
+    while (true) {
+      const uint32_t s = (hi - lo + WAVE - 1) / WAVE;
+      hist[lane] = 0;
+      __threadfence_block();
+      hx_common(x, u, v, [&](uint32_t val) {
+        if (val >= lo && val < hi) atomicAdd(&hist[(val - lo) / s], 1u);
+      });
+      __threadfence_block();
+      const uint32_t hc = hist[lane];
+      uint32_t suf = hc;  // members in bins lane..63
+      for (int o = 1; o < WAVE; o <<= 1) {
+        const uint32_t t = __shfl_down(suf, o, WAVE);
+        if (lane + o < WAVE) suf += t;
+      }
+      const uint32_t bnd = lo + lane * s;
+      const bool ok = bnd < hi && above + suf >= bnd;
+      const uint64_t mask = __ballot(ok);  // lane 0 (bnd = lo) always holds
+      const uint32_t b = 63u - (uint32_t)__clzll(mask);
+      const uint32_t nlo = lo + b * s;
+      if (s == 1) {
+        y = nlo;
+        break;
+      }
+      above += __shfl(suf, b, WAVE) - __shfl(hc, b, WAVE);
+      hi = min(nlo + s, hi);
+      lo = nlo;
+      __threadfence_block();
+    }
+    if (lane == 0) {
+      x.H[e] = y;
+      x.touched[u] = 1;
+      x.touched[v] = 1;
+    }
+    ++changes;
+  }
+  if (lane == 0) {
+    if (evals) atomicAdd(&x.ctr[HX_CTR_EVALS], evals);
+    if (changes) atomicAdd(&x.ctr[HX_CTR_CHANGED], changes);
+  }
+}
+
+// touched -> bitset (clearing touched) and the list of its nonzero words.
+__global__ void __launch_bounds__(256) k_hx_tbits(Hx x) {
+  for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < x.W; i += gridDim.x * blockDim.x) {
+    uint64_t bits = 0;
+    const uint32_t v0 = i * 64;
+    for (uint32_t b = 0; b < 64 && v0 + b < x.n; ++b) {
+      if (x.touched[v0 + b]) {
+        bits |= 1ull << b;
+        x.touched[v0 + b] = 0;
+      }
+    }
+    x.tbits[i] = bits;
+    if (bits) x.tlist[atomicAdd(&x.ctr[HX_CTR_TLIST], 1u)] = i;
+  }
+}
+
+// dirty(x) for the next sweep: L[h-1](x) (x alone when h = 1) meets a
+// touched vertex.  One wave per vertex, scanning either the listed words or,
+// when many are listed, the whole row.
+__global__ void __launch_bounds__(256) k_hx_dirty(Hx x) {
+  const uint32_t lane = lane_id(), wpb = blockDim.x / WAVE;
+  const uint32_t nt = x.ctr[HX_CTR_TLIST];
+  for (uint32_t r = blockIdx.x * wpb + threadIdx.x / WAVE; r < x.n; r += gridDim.x * wpb) {
+    bool hit = false;
+    if (x.h == 1) {
+      hit = (x.tbits[r >> 6] >> (r & 63)) & 1ull;
+    } else if (nt) {
+      const uint64_t* Lr = x.L[x.h - 1] + (size_t)r * x.W;
+      if ((uint64_t)nt * 8 > x.W) {
+        for (uint32_t i = lane; i < x.W && !hit; i += WAVE) hit = (Lr[i] & x.tbits[i]) != 0;
+      } else {
+        for (uint32_t t = lane; t < nt && !hit; t += WAVE) {
+          const uint32_t i = x.tlist[t];
+          hit = (Lr[i] & x.tbits[i]) != 0;
+        }
+      }
+      hit = __ballot(hit) != 0;
+    }
+    if (lane == 0) x.dirty[r] = hit ? 1u : 0u;
+  }
+}
+
+__global__ void k_hx_finish(const uint32_t* __restrict__ H, uint32_t* __restrict__ out, uint32_t m) {
+  for (uint32_t e = blockIdx.x * blockDim.x + threadIdx.x; e < m; e += gridDim.x * blockDim.x)
+    out[e] = H[e] + 2;
+}
+
+}  // namespace hotruss

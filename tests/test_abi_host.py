@@ -127,3 +127,26 @@ def test_session_argument_errors(ht):
     assert lib.hoPoll(nul, 0, C.byref(d)) == -1
     assert lib.hoCancel(nul, 0) == -1
     assert lib.hoSessionDestroy(nul) == -1
+
+
+def test_hindex_argument_errors_return_before_device_work(ht):
+    lib = ht.lib
+    nul = None
+    fake = C.c_void_p(0x1000)
+    sw = C.c_uint32(7)
+    need = C.c_size_t(0)
+    args = lambda h, flags, ws_bytes, sweeps=C.byref(sw): (  # noqa: E731
+        fake, fake, 10, 5, h, flags, 0, fake, sweeps, fake, ws_bytes, C.byref(need), nul)
+    assert lib.hoTrussHIndex(*args(0, 0, 1 << 30)) == -1          # h == 0
+    assert lib.hoTrussHIndex(*args(2, 4, 1 << 30)) == -1          # unknown flag
+    assert lib.hoTrussHIndex(*args(2, 0, 1 << 30, None)) == -1    # no sweep count
+    # workspace below the minimum: HO_ERR_WORKSPACE and the minimum reported
+    assert lib.hoTrussHIndex(*args(2, 0, 16)) == -3
+    assert need.value == lib.hoTrussHIndexWorkspaceBytes(10, 5, 2) > 16
+    # m == 0: nothing to do
+    assert lib.hoTrussHIndex(nul, nul, 10, 0, 2, 0, 0, nul, C.byref(sw), nul, 0, nul, nul) == 0
+    assert sw.value == 0
+    wb = lib.hoTrussHIndexWorkspaceBytes
+    assert wb(200, 1000, 0) == 0
+    assert wb(200, 1000, 1) < wb(200, 1000, 2) < wb(200, 1000, 3)
+    assert wb(1000, 5000, 2) > wb(500, 5000, 2)

@@ -1,0 +1,123 @@
+"""GPU parity of the H-index fixpoint method (Section 4) through the C ABI.
+
+Synchronous sweeps follow the definition's sequence exactly, so every prefix
+H^(s) is compared with the oracle's sequence, element by element.  The final
+values of every mode are compared with the peeling oracle's trussness
+(Theorem 2 makes them equal)."""
+import numpy as np
+import pytest
+
+import oracle
+from graphgen import disjoint_union, from_edges, gen, workloads as W
+from oracle.hindex import hindex_sequence
+
+pytestmark = pytest.mark.gpu
+
+MODES = [dict(asynchronous=False, track=True), dict(asynchronous=False, track=False),
+         dict(asynchronous=True, track=True), dict(asynchronous=True, track=False)]
+MODE_IDS = ["sync", "sync-all", "async", "async-all"]
+
+
+def run(g, h, **kw):
+    import paper_2411_06405_amd as ht
+    print(f"[gpu hindex] {g.name} n={g.n} m={g.m} h={h} {kw}", flush=True)
+    return ht.hindex_graph(g, h, **kw)
+
+
+@pytest.mark.parametrize("h", [1, 2, 3])
+@pytest.mark.parametrize("seed", [0, 1])
+def test_sync_sequence_matches_oracle(seed, h):
+    g = W.d1(seed)
+    seq = hindex_sequence(g, h)
+    for track in (True, False):
+        t, sweeps = run(g, h, track=track)
+        assert sweeps == len(seq) - 1
+        assert np.array_equal(t.astype(np.int64), seq[-1] + 2)
+    for s in range(1, len(seq)):
+        t, sweeps = run(g, h, max_sweeps=s)
+        assert sweeps == s
+        assert np.array_equal(t.astype(np.int64), seq[s] + 2), f"sweep {s}"
+
+
+@pytest.mark.parametrize("mode", MODES, ids=MODE_IDS)
+@pytest.mark.parametrize("h", [1, 2, 3, 4])
+def test_final_equals_trussness_small(mode, h):
+    for seed in (2, 3, 4):
+        g = W.d1(seed)
+        to, _, _ = oracle.decompose(g, h)
+        t, sweeps = run(g, h, **mode)
+        assert np.array_equal(t, to), (seed, h)
+        assert sweeps >= 1
+
+
+@pytest.mark.parametrize("mode", MODES, ids=MODE_IDS)
+@pytest.mark.parametrize("h", [2, 3])
+def test_final_equals_trussness_power_law(mode, h):
+    # several bitset words per row, hubs, a ragged last word (n % 64 != 0)
+    g = W.d2(n=3001, seed=5)
+    to, _, _ = oracle.decompose(g, h)
+    t, _ = run(g, h, **mode)
+    bad = np.nonzero(t != to)[0]
+    assert bad.size == 0, f"{bad.size} mismatches, first {bad[:5]}"
+
+
+@pytest.mark.parametrize("h", [2, 3])
+def test_hub_beyond_one_staging_batch(h):
+    # a centre of degree 1500 > 1024 staged sources, plus a clique and a path
+    # hanging off it so that keys differ along the relaxations
+    r = 1500
+    star = gen.star(r)
+    extra_u = [1, 1, 2, 3, 4, 5, 6, 7]
+    extra_v = [2, 3, 3, 4, 5, 6, 7, 8]
+    e = star.edges()
+    g = from_edges(r + 1, np.concatenate([e[:, 0], extra_u]), np.concatenate([e[:, 1], extra_v]),
+                   name="star-plus")
+    to, _, _ = oracle.decompose(g, h)
+    for mode in MODES:
+        t, _ = run(g, h, **mode)
+        assert np.array_equal(t, to), mode
+
+
+@pytest.mark.parametrize("h", [1, 2, 3, 5])
+def test_special_graphs(h):
+    graphs = [gen.complete(7), gen.cycle(13), gen.path(6), gen.star(9),
+              from_edges(70, [0], [69], name="edge+isolated"),
+              disjoint_union([gen.complete(5), gen.cycle(9), gen.path(4), W.d1(1)])]
+    for g in graphs:
+        to, _, _ = oracle.decompose(g, h)
+        seq = hindex_sequence(g, h)
+        for mode in MODES:
+            t, sweeps = run(g, h, **mode)
+            assert np.array_equal(t, to), (g.name, mode)
+            if not mode["asynchronous"]:
+                assert sweeps == len(seq) - 1
+
+
+def test_empty_and_h_beyond_diameter():
+    import paper_2411_06405_amd as ht
+    t, sweeps = run(gen.empty(5), 2)
+    assert t.size == 0 and sweeps == 0
+    g = gen.complete(6)
+    t, sweeps = run(g, 40)          # h clamps at n - 1
+    assert np.all(t == 6) and sweeps == 1
+    # a caller-given workspace below what the balls need is refused
+    import torch
+    small = torch.empty(ht.lib.hoTrussHIndexWorkspaceBytes(g.n, g.m, 2), dtype=torch.uint8,
+                        device="cuda")
+    with pytest.raises(ht.HotrussError):
+        ht.hindex(g.row_ptr, g.col_idx, g.n, 2, workspace=small)
+
+
+def test_stats_count_sweeps_and_work():
+    import paper_2411_06405_amd as ht
+    g = W.d1(0)
+    t, sweeps = run(g, 2)
+    st = ht.last_stats()
+    w = list(st["work"].values())
+    assert st["rounds"] == sweeps
+    assert w[0] >= g.m          # the first sweep evaluates every edge
+    assert w[1] >= g.n          # and builds every row
+    t2, _ = run(g, 2, track=False)
+    w2 = list(ht.last_stats()["work"].values())
+    assert w2[1] == sweeps * g.n
+    assert w[1] <= w2[1]
