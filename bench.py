@@ -17,6 +17,11 @@ Two more workloads measure the multi-graph forms:
                        p50/p99 latency and graphs/s at fixed fractions of the
                        measured capacity
 
+  --workload hindex    the H-index fixpoint method (Section 4) on the default
+                       Chung-Lu graph: synchronous sweeps timed, asynchronous
+                       and recompute-everything sweeps and the peeling method
+                       once each, all outputs compared bit for bit
+
 Prints one JSON line.  Only one GPU is used; --gpus above 1 exits with a
 message.
 """
@@ -63,10 +68,20 @@ KERNEL_SYMBOL = {"level_events": "k_level", "support_update": "k_support"}
 PROFILES = ROOT / "profiles"
 
 
-def kernel_source_sha() -> str:
-    import hashlib
-    src = ROOT / "paper_2411_06405_amd" / "csrc" / "hotruss_kernels.hip"
-    return hashlib.sha256(src.read_bytes()).hexdigest()[:16]
+def kernel_source_sha(kernel: str) -> str:
+    from paper_2411_06405_amd.profsum import KERNEL_SOURCES, source_sha
+    return source_sha(KERNEL_SOURCES[kernel])
+
+
+def recorded_traffic(kernel: str, workload: str):
+    """HBM bytes per launch from the committed counter summary, if it was taken
+    on the current source of that kernel."""
+    tfile = PROFILES / f"traffic_{kernel}_{workload}.txt"
+    if tfile.exists():
+        t = json.loads(tfile.read_text())
+        if t.get("source_sha") == kernel_source_sha(kernel):
+            return t.get("bytes_per_launch")
+    return None
 
 
 def roofline_from_stats(st: dict, workload: str):
@@ -79,12 +94,7 @@ def roofline_from_stats(st: dict, workload: str):
     avg_ms = km[dom] / launches
     per_launch = alg_bytes / launches
     achieved = per_launch / (avg_ms * 1e-3) / 1e9 if avg_ms > 0 else 0.0
-    traffic = None
-    tfile = PROFILES / f"traffic_{KERNEL_SYMBOL[dom]}_{workload}.txt"
-    if tfile.exists():
-        t = json.loads(tfile.read_text())
-        if t.get("source_sha") == kernel_source_sha():
-            traffic = t.get("bytes_per_launch")
+    traffic = recorded_traffic(KERNEL_SYMBOL[dom], workload)
     return {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
             "kernel": KERNEL_SYMBOL[dom], "launches": int(launches),
@@ -112,6 +122,129 @@ def cpu_baseline(workload: str):
     return {"value": g.m / dt, "unit": "edges/s", "cores": cores, "kind": "oracle",
             "sample": f"{desc}: m={g.m}, {info['rounds']} rounds, {dt:.2f} s; the oracle "
                       f"re-evaluates every live edge each round, so its rate falls as graphs grow"}
+
+
+# Algorithmic bytes of the H-index kernels, per unit of counted work:
+#   edge updates: per edge and sweep its endpoints, H and the two drop masks
+#     (28 B); per pass over a common neighbourhood the two ball rows (2 W
+#     words of 8 B); per word with common members the two rank words (8 B);
+#     per common member the two path keys (8 B)
+#   path-key rows: per row 20 B (offsets, flag, drop mask); per row entry 20 B
+#     (zeroed, and the previous key copied and compared with the new one);
+#     per direct key 24 B (col_idx, edge id, H, rank word and ball word, key);
+#     per relaxation 28 B (the same plus the atomic maximum)
+HX_WORK_KINDS = ("edge_evaluations", "rows_built", "relaxations", "direct_keys",
+                 "row_entries", "passes", "words_with_common", "common_members")
+HX_CPU_SAMPLE_N = 2000  # Chung-Lu sample the H-index oracle finishes in about 10-30 s
+
+
+def _hx_roofline(st: dict, words: int, m: int) -> dict:
+    km = list(st["kernel_ms"].values())
+    kl = list(st["kernel_launches"].values())
+    w = list(st["work"].values())
+    edge_bytes = w[5] * 2 * words * 8 + w[6] * 8 + w[7] * 8 + st["rounds"] * m * 28
+    path_bytes = w[1] * 20 + w[4] * 20 + w[3] * 24 + w[2] * 28
+    kinds = {"k_hx_paths": (km[1], kl[1], path_bytes), "k_hx_edges": (km[2], kl[2], edge_bytes)}
+    dom = max(kinds, key=lambda k: kinds[k][0])
+    ms, launches, alg = kinds[dom]
+    launches = max(launches, 1)
+    avg_ms = ms / launches
+    per_launch = alg / launches
+    achieved = per_launch / (avg_ms * 1e-3) / 1e9 if avg_ms > 0 else 0.0
+    return {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": achieved / HBM_PEAK_GBS, "traffic": recorded_traffic(dom, "hindex"),
+            "kernel": dom,
+            "launches": int(launches), "avg_launch_us": avg_ms * 1e3,
+            "alg_bytes_per_launch": per_launch,
+            "share_of_device_time": ms / max(sum(km), 1e-9),
+            "kernel_ms": {"init": km[0], "k_hx_paths": km[1], "k_hx_edges": km[2],
+                          "tracking": km[3]}}
+
+
+def _calibration_copy(torch, dev) -> None:
+    """A 256 MiB device copy: the reference kernel for the HBM byte counters."""
+    src = torch.empty(256 << 20, dtype=torch.uint8, device=dev).fill_(1)
+    dst = torch.empty_like(src)
+    for _ in range(3):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+
+
+def run_hindex(args) -> dict:
+    import torch
+    import paper_2411_06405_amd as ht
+    from oracle.hindex import hindex_trussness
+
+    make, h, desc = WORKLOADS["chung_lu_100k_h2"]
+    g = make()
+    dev = torch.device("cuda:0")
+    rp = torch.from_numpy(g.row_ptr.view(np.int32)).to(dev)
+    ci = torch.from_numpy(g.col_idx.view(np.int32)).to(dev)
+    ws = ht.hindex_workspace(rp, ci, g.n, h, device=dev)
+    _log(f"H-index workspace {ws.numel() / 2**30:.2f} GiB")
+    for _ in range(args.warmup):
+        ht.hindex(rp, ci, g.n, h, workspace=ws, device=dev)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        t_sync, sweeps = ht.hindex(rp, ci, g.n, h, workspace=ws, device=dev)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    ref = t_sync.clone()
+    modes = {}
+    others = () if args.hx_sync_only else (
+        ("async", dict(asynchronous=True)), ("sync_all", dict(track=False)),
+        ("async_all", dict(asynchronous=True, track=False)))
+    for name, kw in others:
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        t_m, sw = ht.hindex(rp, ci, g.n, h, workspace=ws, device=dev, **kw)
+        torch.cuda.synchronize()
+        modes[name] = {"ms": (time.perf_counter() - t1) * 1e3, "sweeps": sw,
+                       "identical": bool(torch.equal(t_m, ref))}
+        _log(f"{name}: {modes[name]}")
+    identical, peel_ms = None, None
+    if not args.hx_sync_only:
+        pws = ht.alloc_workspace(g.n, g.m, h, device=dev)
+        ht.decompose(rp, ci, g.n, h, workspace=pws, device=dev)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        t_peel, _ = ht.decompose(rp, ci, g.n, h, workspace=pws, device=dev)
+        torch.cuda.synchronize()
+        peel_ms = (time.perf_counter() - t1) * 1e3
+        identical = bool(torch.equal(t_peel, ref))
+        del pws
+    os.environ["HOTRUSS_SWEEPS"] = "1"
+    ht.hindex(rp, ci, g.n, h, workspace=ws, device=dev, stats=True)
+    torch.cuda.synchronize()
+    st = ht.last_stats()
+    if args.calibrate:
+        _calibration_copy(torch, dev)
+    words = ((g.n + 63) // 64 + 7) // 8 * 8
+    line = {
+        "metric": "edges/s to h-trussness (h=2)", "value": g.m * args.steps / dt,
+        "unit": "edges/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": dt * 1e3 / max(args.steps, 1), "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "u32", "data": "synthetic",
+        "config": {"workload": desc + "; H-index fixpoint method, synchronous sweeps",
+                   "n": g.n, "m": g.m, "h": h, "sweeps": sweeps,
+                   "identical_to_peeling": identical,
+                   "peeling_ms": peel_ms, "other_modes": modes,
+                   "value_changes": int(st["events"]),
+                   "work": dict(zip(HX_WORK_KINDS, map(int, st["work"].values())))},
+        "roofline": _hx_roofline(st, words, g.m),
+    }
+    if not args.no_cpu_baseline:
+        gs = W.d2(n=HX_CPU_SAMPLE_N)
+        t1 = time.perf_counter()
+        _, sw = hindex_trussness(gs, h)
+        cdt = time.perf_counter() - t1
+        line["cpu_baseline"] = {
+            "value": gs.m / cdt, "unit": "edges/s", "cores": 1, "kind": "oracle",
+            "sample": f"H-index oracle (synchronous sweeps, numpy) on Chung-Lu "
+                      f"n={HX_CPU_SAMPLE_N} (same avg_deg/gamma/seed): m={gs.m}, {sw} sweeps, "
+                      f"{cdt:.2f} s"}
+    return line
 
 
 def _log(msg: str) -> None:
@@ -332,7 +465,7 @@ def main(argv=None):
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="chung_lu_100k_h2",
-                    choices=sorted(WORKLOADS) + ["batched", "serve"])
+                    choices=sorted(WORKLOADS) + ["batched", "serve", "hindex"])
     ap.add_argument("--graphs", type=int, default=W.D4_B, help="batched: number of graphs")
     ap.add_argument("--requests", type=int, default=200, help="serve: number of requests")
     ap.add_argument("--max-class", type=int, default=0,
@@ -342,6 +475,8 @@ def main(argv=None):
     ap.add_argument("--loads", type=float, nargs="+", default=[0.5, 0.8],
                     help="serve: arrival rates as fractions of the measured capacity")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--hx-sync-only", action="store_true",
+                    help="hindex: time the synchronous sweeps only (profiling runs)")
     ap.add_argument("--calibrate", action="store_true",
                     help="also copy a 256 MiB buffer (reference kernel for HBM counters)")
     args = ap.parse_args(argv)
@@ -355,6 +490,9 @@ def main(argv=None):
         return 0
     if args.workload == "serve":
         print(json.dumps(run_serve(args)), flush=True)
+        return 0
+    if args.workload == "hindex":
+        print(json.dumps(run_hindex(args)), flush=True)
         return 0
 
     import torch
@@ -398,11 +536,7 @@ def main(argv=None):
         "kernel_ms_stats_mode": {k: round(v, 3) for k, v in stt["kernel_ms"].items()},
     }
     if args.calibrate:
-        src = torch.empty(256 << 20, dtype=torch.uint8, device=dev).fill_(1)
-        dst = torch.empty_like(src)
-        for _ in range(3):
-            dst.copy_(src)
-        torch.cuda.synchronize()
+        _calibration_copy(torch, dev)
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(args.workload)
     print(json.dumps(line), flush=True)

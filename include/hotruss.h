@@ -243,7 +243,8 @@ hoStatus hoTrussComponents(const uint32_t *row_ptr, const uint32_t *col_idx, uin
  *               taken in order; a chunk reads the values earlier chunks of
  *               the same sweep wrote).  HO_HINDEX_ALL: recompute every path-key
  *               row and edge in every sweep instead of only those whose inputs
- *               changed (same values; for measurement).
+ *               changed (same values; for measurement).  HO_HINDEX_STATS: time
+ *               every launch group with HIP events and count work (slower).
  *   max_sweeps  0: run until a sweep changes nothing (that sweep is counted);
  *               else stop after that many sweeps.  out_trussness then holds
  *               H + 2 of the last sweep (synchronous: H^(max_sweeps) + 2).
@@ -253,15 +254,20 @@ hoStatus hoTrussComponents(const uint32_t *row_ptr, const uint32_t *col_idx, uin
  *               the h-hop balls, known only on the device: pass at least
  *               hoTrussHIndexWorkspaceBytes(n, m, h) bytes; when the balls
  *               need more, the call returns HO_ERR_WORKSPACE with
- *               *needed_bytes set (4 bytes per ball member, twice for h >= 3,
- *               on top of the minimum); call again with that much.  On success
+ *               *needed_bytes set (8 bytes per ball member, 12 for h >= 3, on
+ *               top of the minimum); call again with that much.  On success
  *               *needed_bytes (if not NULL) is the size this graph needed.
- *   Errors as for hoTrussDecompose; flags outside the two bits give
+ *   Errors as for hoTrussDecompose; flags outside the three bits give
  *   HO_ERR_INVALID_ARG.  hoTrussLastStats afterwards: rounds = sweeps, events =
  *   value changes, work[0] = edge evaluations, work[1] = path-key rows built,
- *   device_ms = the whole call. */
+ *   device_ms = the whole call.  HO_HINDEX_STATS adds kernel_ms/kernel_launches
+ *   [0] balls, H^(0) and ranks, [1] path-key rows, [2] edge updates, [3] change
+ *   tracking, and work [2] relaxations, [3] direct keys, [4] row entries
+ *   written, [5] passes over a common neighbourhood, [6] words with common
+ *   members visited, [7] common members visited. */
 #define HO_HINDEX_ASYNC 0x1u
 #define HO_HINDEX_ALL 0x2u
+#define HO_HINDEX_STATS 0x4u
 size_t hoTrussHIndexWorkspaceBytes(uint32_t n, uint64_t m, uint32_t h);
 hoStatus hoTrussHIndex(const uint32_t *row_ptr, const uint32_t *col_idx, uint32_t n, uint64_t m,
                        uint32_t h, uint32_t flags, uint32_t max_sweeps, uint32_t *out_trussness,

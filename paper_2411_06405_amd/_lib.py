@@ -111,6 +111,7 @@ EXPORTS = ["hoStatusString", "hoTrussWorkspaceBytes", "hoTrussHSupport", "hoTrus
 
 HO_HINDEX_ASYNC = 0x1
 HO_HINDEX_ALL = 0x2
+HO_HINDEX_STATS = 0x4
 
 
 def _check(rc: int, what: str):
@@ -206,8 +207,30 @@ def h_support_graph(g, h: int, **kw) -> np.ndarray:
     return to_numpy_u32(h_support(g.row_ptr, g.col_idx, g.n, h, **kw))
 
 
+def hindex_workspace(row_ptr, col_idx, n: int, h: int, stream=None, device="cuda"):
+    """A workspace that fits this graph's H-index run (two calls: the first
+    reports the size the balls need)."""
+    rp = _dev_u32(row_ptr, device)
+    ci = _dev_u32(col_idx, device)
+    m = ci.numel() // 2
+    nb = int(lib.hoTrussHIndexWorkspaceBytes(n, m, h))
+    ws = torch.empty(max(nb, 1), dtype=torch.uint8, device=device)
+    if m == 0:
+        return ws
+    out = torch.empty(m, dtype=torch.int32, device=device)
+    sweeps = C.c_uint32()
+    needed = C.c_size_t()
+    rc = lib.hoTrussHIndex(rp.data_ptr(), ci.data_ptr(), n, m, h, 0, 1, out.data_ptr(),
+                           C.byref(sweeps), ws.data_ptr(), ws.numel(), C.byref(needed),
+                           _stream(stream))
+    if rc == HO_ERR_WORKSPACE and needed.value > ws.numel():
+        return torch.empty(int(needed.value), dtype=torch.uint8, device=device)
+    _check(rc, "hoTrussHIndex")
+    return ws
+
+
 def hindex(row_ptr, col_idx, n: int, h: int, asynchronous: bool = False, track: bool = True,
-           max_sweeps: int = 0, workspace=None, stream=None, device="cuda"):
+           max_sweeps: int = 0, workspace=None, stream=None, device="cuda", stats: bool = False):
     """Trussness by the H-index fixpoint method: (t device tensor, sweeps).
 
     The workspace size depends on the h-hop balls, which only the device
@@ -218,7 +241,8 @@ def hindex(row_ptr, col_idx, n: int, h: int, asynchronous: bool = False, track: 
     ci = _dev_u32(col_idx, device)
     m = ci.numel() // 2
     out = torch.empty(max(m, 1), dtype=torch.int32, device=device)
-    flags = (HO_HINDEX_ASYNC if asynchronous else 0) | (0 if track else HO_HINDEX_ALL)
+    flags = ((HO_HINDEX_ASYNC if asynchronous else 0) | (0 if track else HO_HINDEX_ALL)
+             | (HO_HINDEX_STATS if stats else 0))
     sweeps = C.c_uint32()
     needed = C.c_size_t()
     grow = workspace is None

@@ -952,7 +952,7 @@ constexpr uint32_t HX_CHUNKS = 8;  // vertex chunks of an asynchronous sweep
 struct HxPlan {
   Plan p;
   size_t off_wp, off_cnt, off_boff, off_dirty, off_touched, off_tbits, off_tlist, off_ord,
-      off_cbound, off_ctr, base;
+      off_cbound, off_ctr, off_stat, off_dmask, base;
 };
 
 bool make_hx_plan(uint32_t n, uint64_t m, uint32_t h, HxPlan* out) {
@@ -971,6 +971,8 @@ bool make_hx_plan(uint32_t n, uint64_t m, uint32_t h, HxPlan* out) {
   q.off_ord = take(4 * m + 4);
   q.off_cbound = take(4 * (HX_CHUNKS + 1));
   q.off_ctr = take(64);
+  q.off_stat = take(64);
+  q.off_dmask = take(8 * (size_t)n + 8);
   q.base = o;
   *out = q;
   return true;
@@ -1352,7 +1354,8 @@ hoStatus hoTrussHIndex(const uint32_t* row_ptr, const uint32_t* col_idx, uint32_
                        uint32_t h, uint32_t flags, uint32_t max_sweeps, uint32_t* out_trussness,
                        uint32_t* out_sweeps, void* workspace, size_t workspace_bytes,
                        size_t* needed_bytes, hipStream_t stream) {
-  if (!out_sweeps || (flags & ~(HO_HINDEX_ASYNC | HO_HINDEX_ALL))) return HO_ERR_INVALID_ARG;
+  if (!out_sweeps || (flags & ~(HO_HINDEX_ASYNC | HO_HINDEX_ALL | HO_HINDEX_STATS)))
+    return HO_ERR_INVALID_ARG;
   hoStatus st = check_common(row_ptr, col_idx, n, m, h, out_trussness, workspace);
   if (st != HO_OK) return st;
   t_stats = hoStats{};
@@ -1368,12 +1371,36 @@ hoStatus hoTrussHIndex(const uint32_t* row_ptr, const uint32_t* col_idx, uint32_
   Dev d = carve(q.p, workspace, row_ptr, col_idx, nullptr, nullptr);
   const uintptr_t wsb = ((uintptr_t)workspace + ALIGN - 1) / ALIGN * ALIGN;
   auto at = [&](size_t off) { return (void*)(wsb + off); };
-  EventGuard ev0, ev1;
+  EventGuard ev0, ev1, ka, kb;
   HIPCHK(hipEventCreate(&ev0.e));
   HIPCHK(hipEventCreate(&ev1.e));
+  const bool stats = flags & HO_HINDEX_STATS;
+  if (stats) {
+    HIPCHK(hipEventCreate(&ka.e));
+    HIPCHK(hipEventCreate(&kb.e));
+  }
+  // stats mode: every launch group timed on its own (0 balls, H^(0) and
+  // ranks, 1 path-key rows, 2 edge updates, 3 change tracking)
+  auto timed = [&](int kind, const std::function<void()>& launch) -> hoStatus {
+    if (!stats) {
+      launch();
+      return HO_OK;
+    }
+    HIPCHK(hipEventRecord(ka.e, stream));
+    launch();
+    HIPCHK(hipEventRecord(kb.e, stream));
+    HIPCHK(hipEventSynchronize(kb.e));
+    float kms = 0.f;
+    HIPCHK(hipEventElapsedTime(&kms, ka.e, kb.e));
+    t_stats.kernel_ms[kind] += kms;
+    t_stats.kernel_launches[kind] += 1;
+    return HO_OK;
+  };
   HIPCHK(hipEventRecord(ev0.e, stream));
   // G's balls and H^(0) = sup_G(e, h)
-  HOCHK(run_init(d, d.sup, nullptr, stream));
+  hoStatus init_st = HO_OK;
+  HOCHK(timed(0, [&] { init_st = run_init(d, d.sup, nullptr, stream); }));
+  HOCHK(init_st);
   Ctl c;
   HOCHK(read_ctl(d, &c, stream));
   if (c.err) return HO_ERR_BAD_CSR;
@@ -1394,18 +1421,26 @@ hoStatus hoTrussHIndex(const uint32_t* row_ptr, const uint32_t* col_idx, uint32_
   x.ord = (uint32_t*)at(q.off_ord);
   x.cbound = (uint32_t*)at(q.off_cbound);
   x.ctr = (uint32_t*)at(q.off_ctr);
+  x.stat = stats ? (unsigned long long*)at(q.off_stat) : nullptr;
   const unsigned T = 256;
-  hipLaunchKernelGGL(k_hx_rank, dim3(grid_for(n, T / WAVE)), dim3(T), 0, stream, x);
-  hipLaunchKernelGGL(k_hx_scan, dim3(1), dim3(1024), 0, stream, x.cnt, x.boff, n);
+  if (stats)
+    hipLaunchKernelGGL(k_fill64, dim3(1), dim3(64), 0, stream, (uint64_t*)x.stat, (size_t)8,
+                       (uint64_t)0);
+  HOCHK(timed(0, [&] {
+    hipLaunchKernelGGL(k_hx_rank, dim3(grid_for(n, T / WAVE)), dim3(T), 0, stream, x);
+    hipLaunchKernelGGL(k_hx_scan, dim3(1), dim3(1024), 0, stream, x.cnt, x.boff, n);
+  }));
   uint64_t members = 0;
   HIPCHK(hipMemcpyAsync(&members, x.boff + n, sizeof members, hipMemcpyDeviceToHost, stream));
   HIPCHK(hipStreamSynchronize(stream));
-  const uint32_t nbuf = d.h >= 3 ? 2 : 1;
+  const uint32_t nbuf = d.h >= 3 ? 3 : 2;  // P[0], P[1] (h >= 3), previous keys
   const size_t need = q.base + nbuf * hx_key_bytes(members) + ALIGN;
   if (needed_bytes) *needed_bytes = need;
   if (workspace_bytes < need) return HO_ERR_WORKSPACE;
   x.P[0] = (uint32_t*)at(q.base);
-  x.P[1] = nbuf == 2 ? (uint32_t*)at(q.base + hx_key_bytes(members)) : nullptr;
+  x.P[1] = d.h >= 3 ? (uint32_t*)at(q.base + hx_key_bytes(members)) : nullptr;
+  x.Pold = (uint32_t*)at(q.base + (nbuf - 1) * hx_key_bytes(members));
+  x.dmask = (uint64_t*)at(q.off_dmask);
   const bool async = flags & HO_HINDEX_ASYNC;
   x.track = (flags & HO_HINDEX_ALL) ? 0u : 1u;
   const uint32_t chunks = async ? HX_CHUNKS : 1;
@@ -1418,26 +1453,46 @@ hoStatus hoTrussHIndex(const uint32_t* row_ptr, const uint32_t* col_idx, uint32_
   HIPCHK(hipGetLastError());
   uint32_t sweeps = 0;
   uint64_t evals = 0, rows = 0, changes = 0;
+  // environment HOTRUSS_SWEEPS set: one line per sweep on stderr
+  const bool trace = std::getenv("HOTRUSS_SWEEPS") != nullptr;
+  auto sweep_t0 = std::chrono::steady_clock::now();
   while (true) {
+    x.first = sweeps == 0 ? 1u : 0u;
     hipLaunchKernelGGL(k_fill32, dim3(1), dim3(64), 0, stream, x.ctr, (size_t)4, 0u);
+    if (x.track)
+      hipLaunchKernelGGL(k_fill64, dim3(grid_for(n, T)), dim3(T), 0, stream, x.dmask, (size_t)n,
+                         (uint64_t)0);
     for (uint32_t cc = 0; cc < chunks; ++cc) {
       const uint32_t vlo = (uint32_t)((uint64_t)cc * n / chunks);
       const uint32_t vhi = (uint32_t)((uint64_t)(cc + 1) * n / chunks);
       if (vhi > vlo)
-        hipLaunchKernelGGL(k_hx_paths, dim3(grid_for(vhi - vlo, 1)), dim3(T), 0, stream, x, vlo,
-                           vhi);
-      hipLaunchKernelGGL(k_hx_edges, dim3(grid_for((m + chunks - 1) / chunks, T / WAVE)),
-                         dim3(T), 0, stream, x, cc, async ? 1u : 0u);
+        HOCHK(timed(1, [&] {
+          hipLaunchKernelGGL(k_hx_paths, dim3(grid_for(vhi - vlo, 1)), dim3(T), 0, stream, x,
+                             vlo, vhi);
+        }));
+      HOCHK(timed(2, [&] {
+        hipLaunchKernelGGL(k_hx_edges, dim3(grid_for((m + chunks - 1) / chunks, T / WAVE)),
+                           dim3(T), 0, stream, x, cc, async ? 1u : 0u);
+      }));
     }
-    if (x.track) {
-      hipLaunchKernelGGL(k_hx_tbits, dim3(grid_for(x.W, T)), dim3(T), 0, stream, x);
-      hipLaunchKernelGGL(k_hx_dirty, dim3(grid_for(n, T / WAVE)), dim3(T), 0, stream, x);
-    }
+    if (x.track)
+      HOCHK(timed(3, [&] {
+        hipLaunchKernelGGL(k_hx_tbits, dim3(grid_for(x.W, T)), dim3(T), 0, stream, x);
+        hipLaunchKernelGGL(k_hx_dirty, dim3(grid_for(n, T / WAVE)), dim3(T), 0, stream, x);
+      }));
     HIPCHK(hipGetLastError());
     uint32_t hc[4];
     HIPCHK(hipMemcpyAsync(hc, x.ctr, sizeof hc, hipMemcpyDeviceToHost, stream));
     HIPCHK(hipStreamSynchronize(stream));
     ++sweeps;
+    if (trace) {
+      const auto now = std::chrono::steady_clock::now();
+      std::fprintf(stderr, "[hotruss] sweep %u: %u changed, %u evaluated, %u rows, %.3f ms\n",
+                   sweeps, hc[HX_CTR_CHANGED], hc[HX_CTR_EVALS], hc[HX_CTR_ROWS],
+                   std::chrono::duration<double, std::milli>(now - sweep_t0).count());
+      std::fflush(stderr);
+      sweep_t0 = now;
+    }
     changes += hc[HX_CTR_CHANGED];
     evals += hc[HX_CTR_EVALS];
     rows += hc[HX_CTR_ROWS];
@@ -1457,6 +1512,17 @@ hoStatus hoTrussHIndex(const uint32_t* row_ptr, const uint32_t* col_idx, uint32_
   t_stats.device_ms = ms;
   t_stats.work[0] = evals;
   t_stats.work[1] = rows;
+  if (stats) {
+    unsigned long long st8[8];
+    HIPCHK(hipMemcpyAsync(st8, x.stat, sizeof st8, hipMemcpyDeviceToHost, stream));
+    HIPCHK(hipStreamSynchronize(stream));
+    t_stats.work[2] = st8[HX_ST_RELAX];
+    t_stats.work[3] = st8[HX_ST_DIRECT];
+    t_stats.work[4] = st8[HX_ST_ENTRIES];
+    t_stats.work[5] = st8[HX_ST_PASSES];
+    t_stats.work[6] = st8[HX_ST_WORDS];
+    t_stats.work[7] = st8[HX_ST_MEMBERS];
+  }
   *out_sweeps = sweeps;
   return HO_OK;
 }

@@ -25,8 +25,13 @@
 // Change tracking (exact; the same answer as recomputing everything): an edge
 // whose H changed marks both endpoints "touched".  P(x,.) reads only keys of
 // edges with an endpoint within h-1 hops of x, so a row needs rebuilding only
-// if L[h-1](x) (for h = 1: x itself) holds a touched vertex; an edge needs
-// re-evaluation only if one of its endpoints' rows was rebuilt.
+// if L[h-1](x) (for h = 1: x itself) holds a touched vertex.  A rebuilt row
+// records in a 64-bucket mask the value ranges its keys fell through: a key
+// that went from a to b < a marks the buckets of b+1 .. a.  An edge with
+// value c keeps it unless some key of its endpoints' rows fell from >= c to
+// < c: otherwise at least c common members still have both keys >= c, and
+// values never rise.  So after the first sweep an edge is re-evaluated only if
+// the bucket of c is marked in either endpoint's mask.
 //
 // Asynchronous sweeps split the vertices into consecutive chunks processed in
 // order; chunk c rebuilds its rows from the keys as they stand (including the
@@ -39,6 +44,9 @@ namespace hotruss {
 constexpr uint32_t HX_SRC = 1024;   // relaxation sources staged per batch
 constexpr uint32_t HX_STAGE_WORDS = HX_SRC / 64;
 constexpr uint32_t HX_CTR_CHANGED = 0, HX_CTR_EVALS = 1, HX_CTR_ROWS = 2, HX_CTR_TLIST = 3;
+// work counters of the stats mode
+constexpr uint32_t HX_ST_PASSES = 0, HX_ST_WORDS = 1, HX_ST_MEMBERS = 2, HX_ST_ROWS = 3,
+                   HX_ST_DIRECT = 4, HX_ST_RELAX = 5, HX_ST_ENTRIES = 6, HX_ST_EVALS = 7;
 
 struct Hx {
   const uint32_t* rp;      // row_ptr [n+1]
@@ -55,6 +63,8 @@ struct Hx {
   uint64_t* boff;      // start of row x's path keys [n+1]
   uint32_t* H;         // current H-index of every edge [m]
   uint32_t* P[2];      // path keys; P[0] holds the finished rows (P[1]: h >= 3 only)
+  uint32_t* Pold;      // tracking: a rebuilt row's previous keys [S]
+  uint64_t* dmask;     // tracking: value buckets the keys of row x fell through [n]
   uint32_t* dirty;     // row x is rebuilt (and its edges re-evaluated) this sweep [n]
   uint32_t* touched;   // x is an endpoint of an edge changed this sweep [n]
   uint64_t* tbits;     // touched as a bitset [W]
@@ -63,7 +73,17 @@ struct Hx {
   uint32_t* cbound;    // chunk c's edges are ord[cbound[c] .. cbound[c+1]) [chunks+1]
   uint32_t* ctr;       // counters: changed, evaluated, rows built, tlist length
   uint32_t track;      // change tracking on: skip clean rows and edges
+  uint32_t first;      // first sweep: every edge is evaluated
+  unsigned long long* stat;  // stats mode: work counters HX_ST_* [8], else null
 };
+
+// Bucket of a value for the drop masks: 0..31 exact, then two buckets per
+// octave up to 2^20, the rest in bucket 63.  Non-decreasing in v.
+__device__ __forceinline__ uint32_t hx_bucket(uint32_t v) {
+  if (v < 32) return v;
+  const uint32_t e = 31u - (uint32_t)__clz(v);
+  return min(63u, 32u + (e - 5) * 2 + ((v >> (e - 1)) & 1u));
+}
 
 __device__ __forceinline__ uint32_t hx_rank(const Hx& x, uint32_t u, uint32_t w) {
   const size_t i = (size_t)u * x.W + (w >> 6);
@@ -138,8 +158,9 @@ __global__ void k_hx_bounds(Hx x, uint32_t chunks) {
 // vertex u: for every edge (y, w), w != u, key(u,w) >= min(s_k, H(y,w)).
 // Work is spread over the whole workgroup by a prefix sum of the sources'
 // degrees (sources with key 0 contribute nothing and get degree 0).
-__device__ void hx_relax(const Hx& x, uint32_t u, uint32_t nb, uint32_t* __restrict__ dst,
-                         const uint32_t* s_y, const uint32_t* s_k, uint32_t* s_pre) {
+// Returns the number of relaxations.
+__device__ uint32_t hx_relax(const Hx& x, uint32_t u, uint32_t nb, uint32_t* __restrict__ dst,
+                             const uint32_t* s_y, const uint32_t* s_k, uint32_t* s_pre) {
   if (threadIdx.x < WAVE) {
     uint32_t run = 0;
     for (uint32_t i0 = 0; i0 < nb; i0 += WAVE) {
@@ -169,6 +190,7 @@ __device__ void hx_relax(const Hx& x, uint32_t u, uint32_t nb, uint32_t* __restr
     const uint32_t val = min(s_k[lo], x.H[x.eid[r]]);
     if (val) atomicMax(&dst[hx_rank(x, u, w)], val);
   }
+  return total;
 }
 
 // Path-key rows of the vertices in [vlo, vhi) (one workgroup per vertex):
@@ -178,7 +200,9 @@ __device__ void hx_relax(const Hx& x, uint32_t u, uint32_t nb, uint32_t* __restr
 __global__ void __launch_bounds__(256) k_hx_paths(Hx x, uint32_t vlo, uint32_t vhi) {
   __shared__ uint32_t s_y[HX_SRC], s_k[HX_SRC], s_pre[HX_SRC + 1];
   __shared__ uint32_t s_cnt[HX_STAGE_WORDS];
+  __shared__ unsigned long long s_mask;
   uint32_t built = 0;
+  unsigned long long direct = 0, relax = 0, entries = 0;
   for (uint32_t u = vlo + blockIdx.x; u < vhi; u += gridDim.x) {
     if (x.track && !x.dirty[u]) continue;
     ++built;
@@ -186,9 +210,17 @@ __global__ void __launch_bounds__(256) k_hx_paths(Hx x, uint32_t vlo, uint32_t v
     const uint32_t len = (uint32_t)(x.boff[u + 1] - base);
     uint32_t cur = x.h >= 2 ? ((x.h - 2) & 1u) : 0u;  // so that the last hop lands in P[0]
     uint32_t* row = x.P[cur] + base;
-    for (uint32_t i = threadIdx.x; i < len; i += blockDim.x) row[i] = 0;
+    uint32_t* fin = x.P[0] + base;
+    uint32_t* old = x.Pold + base;
+    if (threadIdx.x == 0) s_mask = 0;
+    for (uint32_t i = threadIdx.x; i < len; i += blockDim.x) {
+      if (x.track) old[i] = fin[i];
+      row[i] = 0;
+    }
     __syncthreads();
     const uint32_t beg = x.rp[u], end = x.rp[u + 1];
+    direct += end - beg;
+    entries += (unsigned long long)len * (x.h >= 3 ? x.h - 1 : 1);
     for (uint32_t q = beg + threadIdx.x; q < end; q += blockDim.x)
       row[hx_rank(x, u, x.ci[q])] = x.H[x.eid[q]];
     __syncthreads();
@@ -200,7 +232,7 @@ __global__ void __launch_bounds__(256) k_hx_paths(Hx x, uint32_t vlo, uint32_t v
           s_k[i] = x.H[x.eid[q0 + i]];
         }
         __syncthreads();
-        hx_relax(x, u, nb, row, s_y, s_k, s_pre);
+        relax += hx_relax(x, u, nb, row, s_y, s_k, s_pre);
         __syncthreads();
       }
     }
@@ -240,31 +272,56 @@ __global__ void __launch_bounds__(256) k_hx_paths(Hx x, uint32_t vlo, uint32_t v
           } while (b);
         }
         __syncthreads();
-        if (nb) hx_relax(x, u, nb, dst, s_y, s_k, s_pre);
+        if (nb) relax += hx_relax(x, u, nb, dst, s_y, s_k, s_pre);
         __syncthreads();
       }
       cur ^= 1u;
     }
+    if (x.track) {
+      unsigned long long mk = 0;
+      for (uint32_t i = threadIdx.x; i < len; i += blockDim.x) {
+        const uint32_t a = old[i], b = fin[i];
+        if (b < a) {
+          const uint32_t lo = hx_bucket(b + 1), hi = hx_bucket(a);
+          mk |= (~0ull >> (63 - hi)) & ~((1ull << lo) - 1);
+        }
+      }
+      if (mk) atomicOr(&s_mask, mk);
+      __syncthreads();
+      if (threadIdx.x == 0) x.dmask[u] = s_mask;
+      __syncthreads();
+    }
   }
-  if (threadIdx.x == 0 && built) atomicAdd(&x.ctr[HX_CTR_ROWS], built);
+  if (threadIdx.x == 0 && built) {
+    atomicAdd(&x.ctr[HX_CTR_ROWS], built);
+    if (x.stat) {
+      atomicAdd(&x.stat[HX_ST_ROWS], (unsigned long long)built);
+      atomicAdd(&x.stat[HX_ST_DIRECT], direct);
+      atomicAdd(&x.stat[HX_ST_RELAX], relax);
+      atomicAdd(&x.stat[HX_ST_ENTRIES], entries);
+    }
+  }
 }
 
 // f(min(P(u,w), P(v,w))) for every common member w != u, v of the two balls
-// (all 64 lanes call; each lane takes every 64th word).
+// (all 64 lanes call; each lane takes every 64th word).  Returns the number of
+// words with common members this lane visited.
 template <class F>
-__device__ __forceinline__ void hx_common(const Hx& x, uint32_t u, uint32_t v, F&& f) {
+__device__ __forceinline__ uint32_t hx_common(const Hx& x, uint32_t u, uint32_t v, F&& f) {
   const uint64_t* Lu = x.L[x.h] + (size_t)u * x.W;
   const uint64_t* Lv = x.L[x.h] + (size_t)v * x.W;
   const uint32_t* Wu = x.wp + (size_t)u * x.W;
   const uint32_t* Wv = x.wp + (size_t)v * x.W;
   const uint32_t* Pu = x.P[0] + x.boff[u];
   const uint32_t* Pv = x.P[0] + x.boff[v];
+  uint32_t words = 0;
   for (uint32_t i = lane_id(); i < x.W; i += WAVE) {
     const uint64_t a = Lu[i], b = Lv[i];
     uint64_t c = a & b;
     if (i == (u >> 6)) c &= ~(1ull << (u & 63));
     if (i == (v >> 6)) c &= ~(1ull << (v & 63));
     if (!c) continue;
+    ++words;
     const uint32_t ra = Wu[i], rb = Wv[i];
     do {
       const uint64_t below = (c & (~c + 1)) - 1;  // bits under the lowest set bit
@@ -272,6 +329,7 @@ __device__ __forceinline__ void hx_common(const Hx& x, uint32_t u, uint32_t v, F
       c &= c - 1;
     } while (c);
   }
+  return words;
 }
 
 // Update the edges of chunk `chunk` (ord[cbound[chunk] .. cbound[chunk+1]))
@@ -284,16 +342,22 @@ __global__ void __launch_bounds__(256) k_hx_edges(Hx x, uint32_t chunk, uint32_t
   const uint32_t lane = lane_id(), wv = threadIdx.x / WAVE, wpb = blockDim.x / WAVE;
   uint32_t* hist = s_hist[wv];
   uint32_t evals = 0, changes = 0;
+  unsigned long long passes = 0, words = 0, members = 0;  // stats mode (per lane)
   const uint32_t klo = use_ord ? x.cbound[chunk] : 0, khi = use_ord ? x.cbound[chunk + 1] : x.m;
   for (uint32_t k = klo + blockIdx.x * wpb + wv; k < khi; k += gridDim.x * wpb) {
     const uint32_t e = use_ord ? x.ord[k] : k;
     const uint32_t u = x.eu[e], v = x.ev[e];
-    if (x.track && !x.dirty[u] && !x.dirty[v]) continue;
     const uint32_t c = x.H[e];
     if (c == 0) continue;
+    if (x.track && !x.first && !(((x.dmask[u] | x.dmask[v]) >> hx_bucket(c)) & 1ull)) continue;
     ++evals;
-    uint32_t ge = 0;
-    hx_common(x, u, v, [&](uint32_t val) { ge += val >= c; });
+    uint32_t ge = 0, seen = 0;
+    ++passes;
+    words += hx_common(x, u, v, [&](uint32_t val) {
+      ge += val >= c;
+      ++seen;
+    });
+    members += seen;
     ge = wave_sum(ge);
     if (ge >= c) continue;
     // invariant: lo is feasible, hi is not, above = members keyed >= hi
@@ -302,8 +366,10 @@ __global__ void __launch_bounds__(256) k_hx_edges(Hx x, uint32_t chunk, uint32_t
       const uint32_t s = (hi - lo + WAVE - 1) / WAVE;
       hist[lane] = 0;
       __threadfence_block();
-      hx_common(x, u, v, [&](uint32_t val) {
+      ++passes;
+      words += hx_common(x, u, v, [&](uint32_t val) {
         if (val >= lo && val < hi) atomicAdd(&hist[(val - lo) / s], 1u);
+        ++members;
       });
       __threadfence_block();
       const uint32_t hc = hist[lane];
@@ -336,6 +402,16 @@ __global__ void __launch_bounds__(256) k_hx_edges(Hx x, uint32_t chunk, uint32_t
   if (lane == 0) {
     if (evals) atomicAdd(&x.ctr[HX_CTR_EVALS], evals);
     if (changes) atomicAdd(&x.ctr[HX_CTR_CHANGED], changes);
+  }
+  if (x.stat) {
+    words = wave_sum((uint32_t)words);
+    members = wave_sum((uint32_t)members);
+    if (lane == 0 && evals) {
+      atomicAdd(&x.stat[HX_ST_EVALS], (unsigned long long)evals);
+      atomicAdd(&x.stat[HX_ST_PASSES], passes);
+      atomicAdd(&x.stat[HX_ST_WORDS], words);
+      atomicAdd(&x.stat[HX_ST_MEMBERS], members);
+    }
   }
 }
 

@@ -542,7 +542,7 @@ __global__ void __launch_bounds__(LV_THREADS) k_level(const Dev* __restrict__ de
   // could matter: the decomposition ends with it
   if (c->nR == c->live) return;
   if (!c->recovering && (c->iovf[j] || (d.serial & 4u))) {
-    // work list overflowed: leave this level to the serial kernel the host runs
+    // work list overflowed (or forced): halt; the host re-runs this level in windows
     if (blockIdx.x == 0 && threadIdx.x == 0) {
       c->halt = 1;
       c->halt_step = j;

@@ -4,9 +4,9 @@
 
 Writes OUTDIR/kernels_TAG.txt (per-kernel dispatch count and durations from
 --kernel-trace), OUTDIR/hbm_counters_TAG.txt (mean FETCH_SIZE / WRITE_SIZE per
-dispatch, KiB) and OUTDIR/traffic_k_level_TAG.txt / traffic_k_support_TAG.txt
-(HBM bytes per launch of the round kernels, scaled by what the same counters
-read for a 256 MiB device-to-device copy).
+dispatch, KiB) and OUTDIR/traffic_KERNEL_TAG.txt for the kernels named in
+KERNEL_SOURCES (HBM bytes per launch, scaled by what the same counters read
+for a 256 MiB device-to-device copy).
 """
 from __future__ import annotations
 
@@ -19,6 +19,14 @@ from pathlib import Path
 import numpy as np
 
 COPY_BYTES = 256 << 20
+# kernels whose HBM traffic is recorded, and the source file each is built from
+KERNEL_SOURCES = {"k_level": "hotruss_kernels.hip", "k_support": "hotruss_kernels.hip",
+                  "k_hx_paths": "hotruss_hindex.hip", "k_hx_edges": "hotruss_hindex.hip"}
+
+
+def source_sha(srcname: str) -> str:
+    src = Path(__file__).resolve().parent / "csrc" / srcname
+    return hashlib.sha256(src.read_bytes()).hexdigest()[:16]
 
 
 def short(name: str) -> str:
@@ -77,9 +85,8 @@ def main(trace_db, fetch_db, write_db, outdir, tag, cmd):
         lines.append(f"{short(n):40s} {len(f):8d} {f.mean() if len(f) else 0:14.2f} "
                      f"{w.mean() if len(w) else 0:14.2f}")
     (outdir / f"hbm_counters_{tag}.txt").write_text("\n".join(lines) + "\n")
-    src = Path(__file__).resolve().parent / "csrc" / "hotruss_kernels.hip"
-    sha = hashlib.sha256(src.read_bytes()).hexdigest()[:16]
-    for kname in ("k_level", "k_support"):
+    for kname, srcname in KERNEL_SOURCES.items():
+        sha = source_sha(srcname)
         full = [n for n in fetch if short(n) == kname]
         if not full or sf is None or sw is None:
             continue
