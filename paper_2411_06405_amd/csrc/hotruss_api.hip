@@ -952,7 +952,7 @@ constexpr uint32_t HX_CHUNKS = 8;  // vertex chunks of an asynchronous sweep
 struct HxPlan {
   Plan p;
   size_t off_wp, off_cnt, off_boff, off_dirty, off_touched, off_tbits, off_tlist, off_ord,
-      off_cbound, off_ctr, off_stat, off_dmask, base;
+      off_cbound, off_ctr, off_stat, off_dmask, off_tmin, base;
 };
 
 bool make_hx_plan(uint32_t n, uint64_t m, uint32_t h, HxPlan* out) {
@@ -973,6 +973,7 @@ bool make_hx_plan(uint32_t n, uint64_t m, uint32_t h, HxPlan* out) {
   q.off_ctr = take(64);
   q.off_stat = take(64);
   q.off_dmask = take(8 * (size_t)n + 8);
+  q.off_tmin = take(4 * (size_t)n + 4);
   q.base = o;
   *out = q;
   return true;
@@ -1441,6 +1442,7 @@ hoStatus hoTrussHIndex(const uint32_t* row_ptr, const uint32_t* col_idx, uint32_
   x.P[1] = d.h >= 3 ? (uint32_t*)at(q.base + hx_key_bytes(members)) : nullptr;
   x.Pold = (uint32_t*)at(q.base + (nbuf - 1) * hx_key_bytes(members));
   x.dmask = (uint64_t*)at(q.off_dmask);
+  x.tmin = (uint32_t*)at(q.off_tmin);
   const bool async = flags & HO_HINDEX_ASYNC;
   x.track = (flags & HO_HINDEX_ALL) ? 0u : 1u;
   const uint32_t chunks = async ? HX_CHUNKS : 1;
@@ -1456,12 +1458,19 @@ hoStatus hoTrussHIndex(const uint32_t* row_ptr, const uint32_t* col_idx, uint32_
   // environment HOTRUSS_SWEEPS set: one line per sweep on stderr
   const bool trace = std::getenv("HOTRUSS_SWEEPS") != nullptr;
   auto sweep_t0 = std::chrono::steady_clock::now();
+  uint32_t prev_changed = 0, prev_evals = 0;
   while (true) {
     x.first = sweeps == 0 ? 1u : 0u;
+    // fold the first histogram into the counting pass while more than a
+    // quarter of the evaluated edges change
+    x.hist1 = (sweeps == 0 || (uint64_t)prev_changed * 4 > prev_evals) ? 1u : 0u;
     hipLaunchKernelGGL(k_fill32, dim3(1), dim3(64), 0, stream, x.ctr, (size_t)4, 0u);
-    if (x.track)
+    if (x.track) {
       hipLaunchKernelGGL(k_fill64, dim3(grid_for(n, T)), dim3(T), 0, stream, x.dmask, (size_t)n,
                          (uint64_t)0);
+      hipLaunchKernelGGL(k_fill32, dim3(grid_for(n, T)), dim3(T), 0, stream, x.tmin, (size_t)n,
+                         0xffffffffu);
+    }
     for (uint32_t cc = 0; cc < chunks; ++cc) {
       const uint32_t vlo = (uint32_t)((uint64_t)cc * n / chunks);
       const uint32_t vhi = (uint32_t)((uint64_t)(cc + 1) * n / chunks);
@@ -1494,6 +1503,8 @@ hoStatus hoTrussHIndex(const uint32_t* row_ptr, const uint32_t* col_idx, uint32_
       sweep_t0 = now;
     }
     changes += hc[HX_CTR_CHANGED];
+    prev_changed = hc[HX_CTR_CHANGED];
+    prev_evals = hc[HX_CTR_EVALS];
     evals += hc[HX_CTR_EVALS];
     rows += hc[HX_CTR_ROWS];
     if (hc[HX_CTR_CHANGED] == 0 || (max_sweeps && sweeps >= max_sweeps)) break;

@@ -74,6 +74,8 @@ struct Hx {
   uint32_t* ctr;       // counters: changed, evaluated, rows built, tlist length
   uint32_t track;      // change tracking on: skip clean rows and edges
   uint32_t first;      // first sweep: every edge is evaluated
+  uint32_t hist1;      // the counting pass also fills the first histogram
+  uint32_t* tmin;      // smallest new value among the changed edges at x this sweep [n]
   unsigned long long* stat;  // stats mode: work counters HX_ST_* [8], else null
 };
 
@@ -200,7 +202,7 @@ __device__ uint32_t hx_relax(const Hx& x, uint32_t u, uint32_t nb, uint32_t* __r
 __global__ void __launch_bounds__(256) k_hx_paths(Hx x, uint32_t vlo, uint32_t vhi) {
   __shared__ uint32_t s_y[HX_SRC], s_k[HX_SRC], s_pre[HX_SRC + 1];
   __shared__ uint32_t s_cnt[HX_STAGE_WORDS];
-  __shared__ unsigned long long s_mask;
+  __shared__ uint32_t s_mask[2];
   uint32_t built = 0;
   unsigned long long direct = 0, relax = 0, entries = 0;
   for (uint32_t u = vlo + blockIdx.x; u < vhi; u += gridDim.x) {
@@ -212,7 +214,7 @@ __global__ void __launch_bounds__(256) k_hx_paths(Hx x, uint32_t vlo, uint32_t v
     uint32_t* row = x.P[cur] + base;
     uint32_t* fin = x.P[0] + base;
     uint32_t* old = x.Pold + base;
-    if (threadIdx.x == 0) s_mask = 0;
+    if (threadIdx.x < 2) s_mask[threadIdx.x] = 0;
     for (uint32_t i = threadIdx.x; i < len; i += blockDim.x) {
       if (x.track) old[i] = fin[i];
       row[i] = 0;
@@ -286,9 +288,10 @@ __global__ void __launch_bounds__(256) k_hx_paths(Hx x, uint32_t vlo, uint32_t v
           mk |= (~0ull >> (63 - hi)) & ~((1ull << lo) - 1);
         }
       }
-      if (mk) atomicOr(&s_mask, mk);
+      if ((uint32_t)mk) atomicOr(&s_mask[0], (uint32_t)mk);
+      if (mk >> 32) atomicOr(&s_mask[1], (uint32_t)(mk >> 32));
       __syncthreads();
-      if (threadIdx.x == 0) x.dmask[u] = s_mask;
+      if (threadIdx.x == 0) x.dmask[u] = (uint64_t)s_mask[1] << 32 | s_mask[0];
       __syncthreads();
     }
   }
@@ -336,7 +339,9 @@ __device__ __forceinline__ uint32_t hx_common(const Hx& x, uint32_t u, uint32_t 
 // or, when ord is not used, every edge; one wave per edge.  The new value is the largest y <= H(e)
 // with at least y common members keyed >= y: one pass counts the members
 // keyed >= H(e) (enough when H(e) stands); otherwise passes with a 64-bin
-// histogram narrow [lo, hi) by 64x each until one value is left.
+// histogram narrow [lo, hi) by 64x each until one value is left.  When most
+// edges are expected to change (hist1), the counting pass fills the first
+// histogram as well.
 __global__ void __launch_bounds__(256) k_hx_edges(Hx x, uint32_t chunk, uint32_t use_ord) {
   __shared__ uint32_t s_hist[256 / WAVE][WAVE];
   const uint32_t lane = lane_id(), wv = threadIdx.x / WAVE, wpb = blockDim.x / WAVE;
@@ -351,26 +356,30 @@ __global__ void __launch_bounds__(256) k_hx_edges(Hx x, uint32_t chunk, uint32_t
     if (c == 0) continue;
     if (x.track && !x.first && !(((x.dmask[u] | x.dmask[v]) >> hx_bucket(c)) & 1ull)) continue;
     ++evals;
-    uint32_t ge = 0, seen = 0;
-    ++passes;
-    words += hx_common(x, u, v, [&](uint32_t val) {
-      ge += val >= c;
-      ++seen;
-    });
-    members += seen;
-    ge = wave_sum(ge);
-    if (ge >= c) continue;
-    // invariant: lo is feasible, hi is not, above = members keyed >= hi
-    uint32_t lo = 0, hi = c, above = ge, y = 0;
+    // invariant once counted: lo is feasible, hi is not, above = members keyed >= hi
+    uint32_t lo = 0, hi = c, above = 0, y = c;
+    bool counted = false;
     while (true) {
+      const bool histo = counted || x.hist1;
       const uint32_t s = (hi - lo + WAVE - 1) / WAVE;
-      hist[lane] = 0;
-      __threadfence_block();
+      if (histo) {
+        hist[lane] = 0;
+        __threadfence_block();
+      }
+      uint32_t ge = 0, seen = 0;
       ++passes;
       words += hx_common(x, u, v, [&](uint32_t val) {
-        if (val >= lo && val < hi) atomicAdd(&hist[(val - lo) / s], 1u);
-        ++members;
+        ++seen;
+        if (val >= hi) ++ge;
+        else if (histo && val >= lo) atomicAdd(&hist[(val - lo) / s], 1u);
       });
+      members += seen;
+      if (!counted) {
+        above = wave_sum(ge);
+        counted = true;
+        if (above >= c) break;  // H(e) stands
+        if (!histo) continue;
+      }
       __threadfence_block();
       const uint32_t hc = hist[lane];
       uint32_t suf = hc;  // members in bins lane..63
@@ -392,10 +401,13 @@ __global__ void __launch_bounds__(256) k_hx_edges(Hx x, uint32_t chunk, uint32_t
       lo = nlo;
       __threadfence_block();
     }
+    if (y == c) continue;
     if (lane == 0) {
       x.H[e] = y;
       x.touched[u] = 1;
       x.touched[v] = 1;
+      atomicMin(&x.tmin[u], y);
+      atomicMin(&x.tmin[v], y);
     }
     ++changes;
   }
@@ -432,7 +444,10 @@ __global__ void __launch_bounds__(256) k_hx_tbits(Hx x) {
 }
 
 // dirty(x) for the next sweep: L[h-1](x) (x alone when h = 1) meets a
-// touched vertex.  One wave per vertex, scanning either the listed words or,
+// touched vertex.  For h = 2 the test is sharper: a changed edge (y,w), y a
+// neighbour of x, now valued b, moves a two-hop key of x only if
+// H(x,y) > b, so x is dirty if it is touched itself or some neighbour y has
+// tmin(y) < H(x,y).  One wave per vertex, scanning either the listed words or,
 // when many are listed, the whole row.
 __global__ void __launch_bounds__(256) k_hx_dirty(Hx x) {
   const uint32_t lane = lane_id(), wpb = blockDim.x / WAVE;
@@ -441,6 +456,11 @@ __global__ void __launch_bounds__(256) k_hx_dirty(Hx x) {
     bool hit = false;
     if (x.h == 1) {
       hit = (x.tbits[r >> 6] >> (r & 63)) & 1ull;
+    } else if (x.h == 2 && nt) {
+      hit = (x.tbits[r >> 6] >> (r & 63)) & 1ull;
+      for (uint32_t q = x.rp[r] + lane; q < x.rp[r + 1] && !hit; q += WAVE)
+        hit = x.tmin[x.ci[q]] < x.H[x.eid[q]];
+      hit = __ballot(hit) != 0;
     } else if (nt) {
       const uint64_t* Lr = x.L[x.h - 1] + (size_t)r * x.W;
       if ((uint64_t)nt * 8 > x.W) {
