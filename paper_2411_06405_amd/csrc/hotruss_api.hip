@@ -952,7 +952,8 @@ constexpr uint32_t HX_CHUNKS = 8;  // vertex chunks of an asynchronous sweep
 struct HxPlan {
   Plan p;
   size_t off_wp, off_cnt, off_boff, off_dirty, off_touched, off_tbits, off_tlist, off_ord,
-      off_cbound, off_ctr, off_stat, off_dmask, off_tmin, base;
+      off_cbound, off_ctr, off_stat, off_dmask, off_tmin, off_bigctr, off_bigu, off_bigoff,
+      base;
 };
 
 bool make_hx_plan(uint32_t n, uint64_t m, uint32_t h, HxPlan* out) {
@@ -974,6 +975,9 @@ bool make_hx_plan(uint32_t n, uint64_t m, uint32_t h, HxPlan* out) {
   q.off_stat = take(64);
   q.off_dmask = take(8 * (size_t)n + 8);
   q.off_tmin = take(4 * (size_t)n + 4);
+  q.off_bigctr = take(8);
+  q.off_bigu = take(4 * (size_t)n + 4);
+  q.off_bigoff = take(4 * (size_t)n + 4);
   q.base = o;
   *out = q;
   return true;
@@ -1443,6 +1447,9 @@ hoStatus hoTrussHIndex(const uint32_t* row_ptr, const uint32_t* col_idx, uint32_
   x.Pold = (uint32_t*)at(q.base + (nbuf - 1) * hx_key_bytes(members));
   x.dmask = (uint64_t*)at(q.off_dmask);
   x.tmin = (uint32_t*)at(q.off_tmin);
+  x.bigctr = (unsigned long long*)at(q.off_bigctr);
+  x.bigu = (uint32_t*)at(q.off_bigu);
+  x.bigoff = (uint32_t*)at(q.off_bigoff);
   const bool async = flags & HO_HINDEX_ASYNC;
   x.track = (flags & HO_HINDEX_ALL) ? 0u : 1u;
   const uint32_t chunks = async ? HX_CHUNKS : 1;
@@ -1476,8 +1483,15 @@ hoStatus hoTrussHIndex(const uint32_t* row_ptr, const uint32_t* col_idx, uint32_
       const uint32_t vhi = (uint32_t)((uint64_t)(cc + 1) * n / chunks);
       if (vhi > vlo)
         HOCHK(timed(1, [&] {
+          hipLaunchKernelGGL(k_fill64, dim3(1), dim3(64), 0, stream, (uint64_t*)x.bigctr,
+                             (size_t)1, (uint64_t)0);
           hipLaunchKernelGGL(k_hx_paths, dim3(grid_for(vhi - vlo, 1)), dim3(T), 0, stream, x,
                              vlo, vhi);
+          if (x.h == 2) {
+            hipLaunchKernelGGL(k_hx_split, dim3(num_cu() * 8), dim3(T), 0, stream, x);
+            if (x.track)
+              hipLaunchKernelGGL(k_hx_split_mask, dim3(num_cu() * 2), dim3(T), 0, stream, x);
+          }
         }));
       HOCHK(timed(2, [&] {
         hipLaunchKernelGGL(k_hx_edges, dim3(grid_for((m + chunks - 1) / chunks, T / WAVE)),

@@ -42,6 +42,8 @@
 namespace hotruss {
 
 constexpr uint32_t HX_SRC = 1024;   // relaxation sources staged per batch
+constexpr uint32_t HX_BIG = 16384;  // h = 2: rows with more relaxations are split
+constexpr uint32_t HX_SLICE = 64;   // sources per slice of a split row
 constexpr uint32_t HX_STAGE_WORDS = HX_SRC / 64;
 constexpr uint32_t HX_CTR_CHANGED = 0, HX_CTR_EVALS = 1, HX_CTR_ROWS = 2, HX_CTR_TLIST = 3;
 // work counters of the stats mode
@@ -76,6 +78,11 @@ struct Hx {
   uint32_t first;      // first sweep: every edge is evaluated
   uint32_t hist1;      // the counting pass also fills the first histogram
   uint32_t* tmin;      // smallest new value among the changed edges at x this sweep [n]
+  // h = 2: rows whose relaxations are split over workgroups, {rows, slices} in
+  // one counter; row i is bigu[i], its slices start at bigoff[i] [n each]
+  unsigned long long* bigctr;
+  uint32_t* bigu;
+  uint32_t* bigoff;
   unsigned long long* stat;  // stats mode: work counters HX_ST_* [8], else null
 };
 
@@ -195,6 +202,26 @@ __device__ uint32_t hx_relax(const Hx& x, uint32_t u, uint32_t nb, uint32_t* __r
   return total;
 }
 
+// Drop mask of row u (all threads of the workgroup call; s_mask is LDS).
+__device__ void hx_row_mask(const Hx& x, uint32_t u, const uint32_t* old, const uint32_t* fin,
+                            uint32_t len, uint32_t* s_mask) {
+  if (threadIdx.x < 2) s_mask[threadIdx.x] = 0;
+  __syncthreads();
+  unsigned long long mk = 0;
+  for (uint32_t i = threadIdx.x; i < len; i += blockDim.x) {
+    const uint32_t a = old[i], b = fin[i];
+    if (b < a) {
+      const uint32_t lo = hx_bucket(b + 1), hi = hx_bucket(a);
+      mk |= (~0ull >> (63 - hi)) & ~((1ull << lo) - 1);
+    }
+  }
+  if ((uint32_t)mk) atomicOr(&s_mask[0], (uint32_t)mk);
+  if (mk >> 32) atomicOr(&s_mask[1], (uint32_t)(mk >> 32));
+  __syncthreads();
+  if (threadIdx.x == 0) x.dmask[u] = (uint64_t)s_mask[1] << 32 | s_mask[0];
+  __syncthreads();
+}
+
 // Path-key rows of the vertices in [vlo, vhi) (one workgroup per vertex):
 // one hop from u's own edges, a second hop relaxed in place (its sources read
 // the direct keys from H, never the row), further hops double-buffered so a
@@ -202,7 +229,7 @@ __device__ uint32_t hx_relax(const Hx& x, uint32_t u, uint32_t nb, uint32_t* __r
 __global__ void __launch_bounds__(256) k_hx_paths(Hx x, uint32_t vlo, uint32_t vhi) {
   __shared__ uint32_t s_y[HX_SRC], s_k[HX_SRC], s_pre[HX_SRC + 1];
   __shared__ uint32_t s_cnt[HX_STAGE_WORDS];
-  __shared__ uint32_t s_mask[2];
+  __shared__ uint32_t s_mask[2], s_rs;
   uint32_t built = 0;
   unsigned long long direct = 0, relax = 0, entries = 0;
   for (uint32_t u = vlo + blockIdx.x; u < vhi; u += gridDim.x) {
@@ -214,7 +241,7 @@ __global__ void __launch_bounds__(256) k_hx_paths(Hx x, uint32_t vlo, uint32_t v
     uint32_t* row = x.P[cur] + base;
     uint32_t* fin = x.P[0] + base;
     uint32_t* old = x.Pold + base;
-    if (threadIdx.x < 2) s_mask[threadIdx.x] = 0;
+    if (threadIdx.x == 0) s_rs = 0;
     for (uint32_t i = threadIdx.x; i < len; i += blockDim.x) {
       if (x.track) old[i] = fin[i];
       row[i] = 0;
@@ -223,9 +250,26 @@ __global__ void __launch_bounds__(256) k_hx_paths(Hx x, uint32_t vlo, uint32_t v
     const uint32_t beg = x.rp[u], end = x.rp[u + 1];
     direct += end - beg;
     entries += (unsigned long long)len * (x.h >= 3 ? x.h - 1 : 1);
-    for (uint32_t q = beg + threadIdx.x; q < end; q += blockDim.x)
-      row[hx_rank(x, u, x.ci[q])] = x.H[x.eid[q]];
+    uint32_t rs = 0;  // relaxations of the second hop
+    for (uint32_t q = beg + threadIdx.x; q < end; q += blockDim.x) {
+      const uint32_t y = x.ci[q];
+      row[hx_rank(x, u, y)] = x.H[x.eid[q]];
+      rs += x.rp[y + 1] - x.rp[y];
+    }
+    rs = wave_sum(rs);
+    if (lane_id() == 0 && rs) atomicAdd(&s_rs, rs);
     __syncthreads();
+    if (x.h == 2 && (end - beg > HX_SRC || s_rs > HX_BIG)) {
+      // a heavy row: its second hop is relaxed in slices by k_hx_split
+      if (threadIdx.x == 0) {
+        const uint32_t slices = (end - beg + HX_SLICE - 1) / HX_SLICE;
+        const unsigned long long at = atomicAdd(x.bigctr, (1ull << 32) | slices);
+        x.bigu[at >> 32] = u;
+        x.bigoff[at >> 32] = (uint32_t)at;
+      }
+      __syncthreads();
+      continue;
+    }
     if (x.h >= 2) {
       for (uint32_t q0 = beg; q0 < end; q0 += HX_SRC) {
         const uint32_t nb = min(HX_SRC, end - q0);
@@ -279,21 +323,7 @@ __global__ void __launch_bounds__(256) k_hx_paths(Hx x, uint32_t vlo, uint32_t v
       }
       cur ^= 1u;
     }
-    if (x.track) {
-      unsigned long long mk = 0;
-      for (uint32_t i = threadIdx.x; i < len; i += blockDim.x) {
-        const uint32_t a = old[i], b = fin[i];
-        if (b < a) {
-          const uint32_t lo = hx_bucket(b + 1), hi = hx_bucket(a);
-          mk |= (~0ull >> (63 - hi)) & ~((1ull << lo) - 1);
-        }
-      }
-      if ((uint32_t)mk) atomicOr(&s_mask[0], (uint32_t)mk);
-      if (mk >> 32) atomicOr(&s_mask[1], (uint32_t)(mk >> 32));
-      __syncthreads();
-      if (threadIdx.x == 0) x.dmask[u] = (uint64_t)s_mask[1] << 32 | s_mask[0];
-      __syncthreads();
-    }
+    if (x.track) hx_row_mask(x, u, old, fin, len, s_mask);
   }
   if (threadIdx.x == 0 && built) {
     atomicAdd(&x.ctr[HX_CTR_ROWS], built);
@@ -306,31 +336,82 @@ __global__ void __launch_bounds__(256) k_hx_paths(Hx x, uint32_t vlo, uint32_t v
   }
 }
 
+// Second hop of the heavy rows k_hx_paths set aside (h = 2): one workgroup
+// per slice of HX_SLICE sources; the maxima are atomic, so slices of one row
+// may run in any order on any workgroups.
+__global__ void __launch_bounds__(256) k_hx_split(Hx x) {
+  __shared__ uint32_t s_y[HX_SLICE], s_k[HX_SLICE], s_pre[HX_SLICE + 1];
+  const unsigned long long ctr = *x.bigctr;
+  const uint32_t nbig = (uint32_t)(ctr >> 32), total = (uint32_t)ctr;
+  unsigned long long relax = 0;
+  for (uint32_t t = blockIdx.x; t < total; t += gridDim.x) {
+    uint32_t lo = 0, hi = nbig;  // the last row whose slices start at or before t
+    while (hi - lo > 1) {
+      const uint32_t mid = (lo + hi) >> 1;
+      if (x.bigoff[mid] <= t) lo = mid; else hi = mid;
+    }
+    const uint32_t u = x.bigu[lo];
+    const uint32_t q0 = x.rp[u] + (t - x.bigoff[lo]) * HX_SLICE;
+    const uint32_t nb = min(HX_SLICE, x.rp[u + 1] - q0);
+    if (threadIdx.x < nb) {
+      s_y[threadIdx.x] = x.ci[q0 + threadIdx.x];
+      s_k[threadIdx.x] = x.H[x.eid[q0 + threadIdx.x]];
+    }
+    __syncthreads();
+    relax += hx_relax(x, u, nb, x.P[0] + x.boff[u], s_y, s_k, s_pre);
+    __syncthreads();
+  }
+  if (x.stat && threadIdx.x == 0 && relax) atomicAdd(&x.stat[HX_ST_RELAX], relax);
+}
+
+// Drop masks of the heavy rows, once all their slices are done.
+__global__ void __launch_bounds__(256) k_hx_split_mask(Hx x) {
+  __shared__ uint32_t s_mask[2];
+  const uint32_t nbig = (uint32_t)(*x.bigctr >> 32);
+  for (uint32_t i = blockIdx.x; i < nbig; i += gridDim.x) {
+    const uint32_t u = x.bigu[i];
+    const uint64_t base = x.boff[u];
+    hx_row_mask(x, u, x.Pold + base, x.P[0] + base, (uint32_t)(x.boff[u + 1] - base), s_mask);
+  }
+}
+
 // f(min(P(u,w), P(v,w))) for every common member w != u, v of the two balls
-// (all 64 lanes call; each lane takes every 64th word).  Returns the number of
-// words with common members this lane visited.
-template <class F>
-__device__ __forceinline__ uint32_t hx_common(const Hx& x, uint32_t u, uint32_t v, F&& f) {
+// (all 64 lanes call; lanes take consecutive words).  Every HX_STOP_EVERY
+// word rows, at a point all lanes reach together, stop() may end the scan.
+// Returns the number of words with common members this lane visited.
+constexpr uint32_t HX_STOP_EVERY = 4;
+
+template <class F, class S>
+__device__ __forceinline__ uint32_t hx_common(const Hx& x, uint32_t u, uint32_t v, F&& f,
+                                              S&& stop) {
   const uint64_t* Lu = x.L[x.h] + (size_t)u * x.W;
   const uint64_t* Lv = x.L[x.h] + (size_t)v * x.W;
   const uint32_t* Wu = x.wp + (size_t)u * x.W;
   const uint32_t* Wv = x.wp + (size_t)v * x.W;
   const uint32_t* Pu = x.P[0] + x.boff[u];
   const uint32_t* Pv = x.P[0] + x.boff[v];
-  uint32_t words = 0;
-  for (uint32_t i = lane_id(); i < x.W; i += WAVE) {
-    const uint64_t a = Lu[i], b = Lv[i];
-    uint64_t c = a & b;
-    if (i == (u >> 6)) c &= ~(1ull << (u & 63));
-    if (i == (v >> 6)) c &= ~(1ull << (v & 63));
-    if (!c) continue;
-    ++words;
-    const uint32_t ra = Wu[i], rb = Wv[i];
-    do {
-      const uint64_t below = (c & (~c + 1)) - 1;  // bits under the lowest set bit
-      f(min(Pu[ra + (uint32_t)__popcll(a & below)], Pv[rb + (uint32_t)__popcll(b & below)]));
-      c &= c - 1;
-    } while (c);
+  uint32_t words = 0, it = 0;
+  for (uint32_t i0 = 0; i0 < x.W; i0 += WAVE) {
+    const uint32_t i = i0 + lane_id();
+    if (i < x.W) {
+      const uint64_t a = Lu[i], b = Lv[i];
+      uint64_t c = a & b;
+      if (i == (u >> 6)) c &= ~(1ull << (u & 63));
+      if (i == (v >> 6)) c &= ~(1ull << (v & 63));
+      if (c) {
+        ++words;
+        const uint32_t ra = Wu[i], rb = Wv[i];
+        do {
+          const uint64_t below = (c & (~c + 1)) - 1;  // bits under the lowest set bit
+          f(min(Pu[ra + (uint32_t)__popcll(a & below)], Pv[rb + (uint32_t)__popcll(b & below)]));
+          c &= c - 1;
+        } while (c);
+      }
+    }
+    if (++it == HX_STOP_EVERY) {
+      it = 0;
+      if (stop()) break;
+    }
   }
   return words;
 }
@@ -368,11 +449,15 @@ __global__ void __launch_bounds__(256) k_hx_edges(Hx x, uint32_t chunk, uint32_t
       }
       uint32_t ge = 0, seen = 0;
       ++passes;
-      words += hx_common(x, u, v, [&](uint32_t val) {
-        ++seen;
-        if (val >= hi) ++ge;
-        else if (histo && val >= lo) atomicAdd(&hist[(val - lo) / s], 1u);
-      });
+      // the counting pass may stop as soon as c members are keyed >= c
+      words += hx_common(
+          x, u, v,
+          [&](uint32_t val) {
+            ++seen;
+            if (val >= hi) ++ge;
+            else if (histo && val >= lo) atomicAdd(&hist[(val - lo) / s], 1u);
+          },
+          [&]() { return !counted && wave_sum(ge) >= c; });
       members += seen;
       if (!counted) {
         above = wave_sum(ge);

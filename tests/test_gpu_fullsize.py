@@ -62,3 +62,28 @@ def test_fullsize_initial_support_sampled():
     sample = rng.choice(g.m, 500, replace=False)
     ref = oracle.h_support_edges(g, 2, sample.astype(np.uint32))
     assert np.array_equal(sup[sample], ref)
+
+
+def test_fullsize_hindex_equals_certified_peeling():
+    # the H-index fixpoint method (Section 4) at the bench size and launch
+    # configuration, synchronous and asynchronous, against the peeling
+    # method's trussness, which the oracle's certificate checks here too
+    import torch
+    import paper_2411_06405_amd as ht
+    g = W.d2()
+    h = 2
+    t, rho, _, _ = _decompose_like_bench(g, h)
+    assert_certified(g, h, t, rho, 1000)
+    dev = torch.device("cuda:0")
+    rp = torch.from_numpy(g.row_ptr.view(np.int32)).to(dev)
+    ci = torch.from_numpy(g.col_idx.view(np.int32)).to(dev)
+    ws = ht.hindex_workspace(rp, ci, g.n, h, device=dev)
+    for asynchronous in (False, True):
+        print(f"[gpu] H-index {g.name} h={h} asynchronous={asynchronous}", flush=True)
+        th, sweeps = ht.hindex(rp, ci, g.n, h, asynchronous=asynchronous, workspace=ws, device=dev)
+        th = ht.to_numpy_u32(th)
+        bad = np.nonzero(th != t)[0]
+        assert bad.size == 0, f"{bad.size} mismatches, first {bad[:5]}"
+        assert 1 <= sweeps < 100
+    del ws
+    torch.cuda.empty_cache()
