@@ -49,6 +49,8 @@ WORKLOADS = {
     "rmat18_h2": (lambda: W.d3(), 2, "R-MAT scale 18 ef 16 (0.57,0.19,0.19,0.05) seed=1, h=2"),
     "rmat18_h3": (lambda: W.d3(), 3, "R-MAT scale 18 ef 16 (0.57,0.19,0.19,0.05) seed=1, h=3"),
     "er200_h2": (lambda: W.d1(0), 2, "Erdos-Renyi G(200,0.05) seed=0, h=2"),
+    "chung_lu_100k_h1": (lambda: W.d2(), 1,
+                         "Chung-Lu n=100000 avg_deg=10 gamma=2.5 seed=1, h=1 (classical truss)"),
 }
 
 CPU_SAMPLE_N = 4000  # Chung-Lu sample the oracle decomposes completely (about 10-30 s)
@@ -129,8 +131,7 @@ def cpu_baseline(workload: str):
 #     (28 B); per pass over a common neighbourhood the two ball rows (2 W
 #     words of 8 B); per word with common members the two rank words (8 B);
 #     per common member the two path keys (8 B)
-#   path-key rows: per row 20 B (offsets, flag, drop mask); per row entry 20 B
-#     (zeroed, and the previous key copied and compared with the new one);
+#   path-key rows: per row 12 B (offsets, flag); per row entry 4 B (zeroed);
 #     per direct key 24 B (col_idx, edge id, H, rank word and ball word, key);
 #     per relaxation 28 B (the same plus the atomic maximum)
 HX_WORK_KINDS = ("edge_evaluations", "rows_built", "relaxations", "direct_keys",
@@ -143,7 +144,7 @@ def _hx_roofline(st: dict, words: int, m: int) -> dict:
     kl = list(st["kernel_launches"].values())
     w = list(st["work"].values())
     edge_bytes = w[5] * 2 * words * 8 + w[6] * 8 + w[7] * 8 + st["rounds"] * m * 28
-    path_bytes = w[1] * 20 + w[4] * 20 + w[3] * 24 + w[2] * 28
+    path_bytes = w[1] * 12 + w[4] * 4 + w[3] * 24 + w[2] * 28
     kinds = {"k_hx_paths": (km[1], kl[1], path_bytes), "k_hx_edges": (km[2], kl[2], edge_bytes)}
     dom = max(kinds, key=lambda k: kinds[k][0])
     ms, launches, alg = kinds[dom]
@@ -175,12 +176,14 @@ def run_hindex(args) -> dict:
     import paper_2411_06405_amd as ht
     from oracle.hindex import hindex_trussness
 
-    make, h, desc = WORKLOADS["chung_lu_100k_h2"]
+    make, _, desc = WORKLOADS["chung_lu_100k_h2"]
+    h = args.hx_h
+    desc = desc.replace("h=2", f"h={h}")
     g = make()
     dev = torch.device("cuda:0")
     rp = torch.from_numpy(g.row_ptr.view(np.int32)).to(dev)
     ci = torch.from_numpy(g.col_idx.view(np.int32)).to(dev)
-    ws = ht.hindex_workspace(rp, ci, g.n, h, device=dev)
+    ws = ht.hindex_workspace(rp, ci, g.n, h, pruning="keys", device=dev)  # fits every mode
     _log(f"H-index workspace {ws.numel() / 2**30:.2f} GiB")
     for _ in range(args.warmup):
         ht.hindex(rp, ci, g.n, h, workspace=ws, device=dev)
@@ -194,14 +197,17 @@ def run_hindex(args) -> dict:
     modes = {}
     others = () if args.hx_sync_only else (
         ("async", dict(asynchronous=True)), ("sync_all", dict(track=False)),
-        ("async_all", dict(asynchronous=True, track=False)))
+        ("async_all", dict(asynchronous=True, track=False)),
+        ("sync_keys", dict(pruning="keys")), ("async_keys", dict(asynchronous=True, pruning="keys")))
     for name, kw in others:
         torch.cuda.synchronize()
         t1 = time.perf_counter()
         t_m, sw = ht.hindex(rp, ci, g.n, h, workspace=ws, device=dev, **kw)
         torch.cuda.synchronize()
+        wk = list(ht.last_stats()["work"].values())
         modes[name] = {"ms": (time.perf_counter() - t1) * 1e3, "sweeps": sw,
-                       "identical": bool(torch.equal(t_m, ref))}
+                       "identical": bool(torch.equal(t_m, ref)),
+                       "edge_evaluations": int(wk[0]), "rows_built": int(wk[1])}
         _log(f"{name}: {modes[name]}")
     identical, peel_ms = None, None
     if not args.hx_sync_only:
@@ -222,7 +228,7 @@ def run_hindex(args) -> dict:
         _calibration_copy(torch, dev)
     words = ((g.n + 63) // 64 + 7) // 8 * 8
     line = {
-        "metric": "edges/s to h-trussness (h=2)", "value": g.m * args.steps / dt,
+        "metric": f"edges/s to h-trussness (h={h})", "value": g.m * args.steps / dt,
         "unit": "edges/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
         "ms_per_step": dt * 1e3 / max(args.steps, 1), "higher_is_better": True,
         "scaling": "weak", "vs_baseline": None, "dtype": "u32", "data": "synthetic",
@@ -475,6 +481,7 @@ def main(argv=None):
     ap.add_argument("--loads", type=float, nargs="+", default=[0.5, 0.8],
                     help="serve: arrival rates as fractions of the measured capacity")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--hx-h", type=int, default=2, help="hindex: hop threshold h")
     ap.add_argument("--hx-sync-only", action="store_true",
                     help="hindex: time the synchronous sweeps only (profiling runs)")
     ap.add_argument("--calibrate", action="store_true",

@@ -243,7 +243,13 @@ hoStatus hoTrussComponents(const uint32_t *row_ptr, const uint32_t *col_idx, uin
  *               taken in order; a chunk reads the values earlier chunks of
  *               the same sweep wrote).  HO_HINDEX_ALL: recompute every path-key
  *               row and edge in every sweep instead of only those whose inputs
- *               changed (same values; for measurement).  HO_HINDEX_STATS: time
+ *               changed (same values; for measurement).  By default an edge
+ *               is re-evaluated only as the paper's pruning rule allows
+ *               (Section 4.3, Lemma 4: skipped unless some edge its update
+ *               reads fell from >= its value to below it).  HO_HINDEX_KEYS:
+ *               apply that test to the path keys of its endpoints instead
+ *               (finer, but each rebuilt row is compared with its previous
+ *               keys; same values).  HO_HINDEX_STATS: time
  *               every launch group with HIP events and count work (slower).
  *   max_sweeps  0: run until a sweep changes nothing (that sweep is counted);
  *               else stop after that many sweeps.  out_trussness then holds
@@ -254,10 +260,11 @@ hoStatus hoTrussComponents(const uint32_t *row_ptr, const uint32_t *col_idx, uin
  *               the h-hop balls, known only on the device: pass at least
  *               hoTrussHIndexWorkspaceBytes(n, m, h) bytes; when the balls
  *               need more, the call returns HO_ERR_WORKSPACE with
- *               *needed_bytes set (8 bytes per ball member, 12 for h >= 3, on
- *               top of the minimum); call again with that much.  On success
+ *               *needed_bytes set (4 bytes per ball member, 8 for h >= 3, and
+ *               4 more with HO_HINDEX_KEYS, on top of the minimum); call again
+ *               with that much.  On success
  *               *needed_bytes (if not NULL) is the size this graph needed.
- *   Errors as for hoTrussDecompose; flags outside the three bits give
+ *   Errors as for hoTrussDecompose; flags outside the four bits give
  *   HO_ERR_INVALID_ARG.  hoTrussLastStats afterwards: rounds = sweeps, events =
  *   value changes, work[0] = edge evaluations, work[1] = path-key rows built,
  *   device_ms = the whole call.  HO_HINDEX_STATS adds kernel_ms/kernel_launches
@@ -268,6 +275,7 @@ hoStatus hoTrussComponents(const uint32_t *row_ptr, const uint32_t *col_idx, uin
 #define HO_HINDEX_ASYNC 0x1u
 #define HO_HINDEX_ALL 0x2u
 #define HO_HINDEX_STATS 0x4u
+#define HO_HINDEX_KEYS 0x8u
 size_t hoTrussHIndexWorkspaceBytes(uint32_t n, uint64_t m, uint32_t h);
 hoStatus hoTrussHIndex(const uint32_t *row_ptr, const uint32_t *col_idx, uint32_t n, uint64_t m,
                        uint32_t h, uint32_t flags, uint32_t max_sweeps, uint32_t *out_trussness,

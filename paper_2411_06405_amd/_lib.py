@@ -112,6 +112,7 @@ EXPORTS = ["hoStatusString", "hoTrussWorkspaceBytes", "hoTrussHSupport", "hoTrus
 HO_HINDEX_ASYNC = 0x1
 HO_HINDEX_ALL = 0x2
 HO_HINDEX_STATS = 0x4
+HO_HINDEX_KEYS = 0x8
 
 
 def _check(rc: int, what: str):
@@ -207,7 +208,8 @@ def h_support_graph(g, h: int, **kw) -> np.ndarray:
     return to_numpy_u32(h_support(g.row_ptr, g.col_idx, g.n, h, **kw))
 
 
-def hindex_workspace(row_ptr, col_idx, n: int, h: int, stream=None, device="cuda"):
+def hindex_workspace(row_ptr, col_idx, n: int, h: int, pruning: str = "lemma4", stream=None,
+                     device="cuda"):
     """A workspace that fits this graph's H-index run (two calls: the first
     reports the size the balls need)."""
     rp = _dev_u32(row_ptr, device)
@@ -220,7 +222,8 @@ def hindex_workspace(row_ptr, col_idx, n: int, h: int, stream=None, device="cuda
     out = torch.empty(m, dtype=torch.int32, device=device)
     sweeps = C.c_uint32()
     needed = C.c_size_t()
-    rc = lib.hoTrussHIndex(rp.data_ptr(), ci.data_ptr(), n, m, h, 0, 1, out.data_ptr(),
+    flags = HO_HINDEX_KEYS if pruning == "keys" else 0
+    rc = lib.hoTrussHIndex(rp.data_ptr(), ci.data_ptr(), n, m, h, flags, 1, out.data_ptr(),
                            C.byref(sweeps), ws.data_ptr(), ws.numel(), C.byref(needed),
                            _stream(stream))
     if rc == HO_ERR_WORKSPACE and needed.value > ws.numel():
@@ -230,7 +233,8 @@ def hindex_workspace(row_ptr, col_idx, n: int, h: int, stream=None, device="cuda
 
 
 def hindex(row_ptr, col_idx, n: int, h: int, asynchronous: bool = False, track: bool = True,
-           max_sweeps: int = 0, workspace=None, stream=None, device="cuda", stats: bool = False):
+           max_sweeps: int = 0, workspace=None, stream=None, device="cuda", stats: bool = False,
+           pruning: str = "lemma4"):
     """Trussness by the H-index fixpoint method: (t device tensor, sweeps).
 
     The workspace size depends on the h-hop balls, which only the device
@@ -242,7 +246,9 @@ def hindex(row_ptr, col_idx, n: int, h: int, asynchronous: bool = False, track: 
     m = ci.numel() // 2
     out = torch.empty(max(m, 1), dtype=torch.int32, device=device)
     flags = ((HO_HINDEX_ASYNC if asynchronous else 0) | (0 if track else HO_HINDEX_ALL)
-             | (HO_HINDEX_STATS if stats else 0))
+             | (HO_HINDEX_STATS if stats else 0) | (HO_HINDEX_KEYS if pruning == "keys" else 0))
+    if pruning not in ("lemma4", "keys"):
+        raise ValueError("pruning is 'lemma4' (the paper's rule on edge values) or 'keys'")
     sweeps = C.c_uint32()
     needed = C.c_size_t()
     grow = workspace is None

@@ -953,7 +953,7 @@ struct HxPlan {
   Plan p;
   size_t off_wp, off_cnt, off_boff, off_dirty, off_touched, off_tbits, off_tlist, off_ord,
       off_cbound, off_ctr, off_stat, off_dmask, off_tmin, off_bigctr, off_bigu, off_bigoff,
-      base;
+      off_cmask, base;
 };
 
 bool make_hx_plan(uint32_t n, uint64_t m, uint32_t h, HxPlan* out) {
@@ -978,6 +978,7 @@ bool make_hx_plan(uint32_t n, uint64_t m, uint32_t h, HxPlan* out) {
   q.off_bigctr = take(8);
   q.off_bigu = take(4 * (size_t)n + 4);
   q.off_bigoff = take(4 * (size_t)n + 4);
+  q.off_cmask = take(8 * (size_t)n + 8);
   q.base = o;
   *out = q;
   return true;
@@ -1359,7 +1360,8 @@ hoStatus hoTrussHIndex(const uint32_t* row_ptr, const uint32_t* col_idx, uint32_
                        uint32_t h, uint32_t flags, uint32_t max_sweeps, uint32_t* out_trussness,
                        uint32_t* out_sweeps, void* workspace, size_t workspace_bytes,
                        size_t* needed_bytes, hipStream_t stream) {
-  if (!out_sweeps || (flags & ~(HO_HINDEX_ASYNC | HO_HINDEX_ALL | HO_HINDEX_STATS)))
+  if (!out_sweeps ||
+      (flags & ~(HO_HINDEX_ASYNC | HO_HINDEX_ALL | HO_HINDEX_STATS | HO_HINDEX_KEYS)))
     return HO_ERR_INVALID_ARG;
   hoStatus st = check_common(row_ptr, col_idx, n, m, h, out_trussness, workspace);
   if (st != HO_OK) return st;
@@ -1438,20 +1440,24 @@ hoStatus hoTrussHIndex(const uint32_t* row_ptr, const uint32_t* col_idx, uint32_
   uint64_t members = 0;
   HIPCHK(hipMemcpyAsync(&members, x.boff + n, sizeof members, hipMemcpyDeviceToHost, stream));
   HIPCHK(hipStreamSynchronize(stream));
-  const uint32_t nbuf = d.h >= 3 ? 3 : 2;  // P[0], P[1] (h >= 3), previous keys
+  // P[0], P[1] (h >= 3), previous keys (path-key pruning only)
+  const bool keys = !(flags & HO_HINDEX_ALL) && (flags & HO_HINDEX_KEYS);
+  const uint32_t nbuf = (d.h >= 3 ? 2 : 1) + (keys ? 1 : 0);
   const size_t need = q.base + nbuf * hx_key_bytes(members) + ALIGN;
   if (needed_bytes) *needed_bytes = need;
   if (workspace_bytes < need) return HO_ERR_WORKSPACE;
   x.P[0] = (uint32_t*)at(q.base);
   x.P[1] = d.h >= 3 ? (uint32_t*)at(q.base + hx_key_bytes(members)) : nullptr;
-  x.Pold = (uint32_t*)at(q.base + (nbuf - 1) * hx_key_bytes(members));
+  x.Pold = keys ? (uint32_t*)at(q.base + (nbuf - 1) * hx_key_bytes(members)) : nullptr;
   x.dmask = (uint64_t*)at(q.off_dmask);
   x.tmin = (uint32_t*)at(q.off_tmin);
   x.bigctr = (unsigned long long*)at(q.off_bigctr);
   x.bigu = (uint32_t*)at(q.off_bigu);
   x.bigoff = (uint32_t*)at(q.off_bigoff);
+  x.cmask = (uint32_t*)at(q.off_cmask);
   const bool async = flags & HO_HINDEX_ASYNC;
   x.track = (flags & HO_HINDEX_ALL) ? 0u : 1u;
+  x.lemma4 = (x.track && !(flags & HO_HINDEX_KEYS)) ? 1u : 0u;
   const uint32_t chunks = async ? HX_CHUNKS : 1;
   if (async) {
     hipLaunchKernelGGL(k_hx_order, dim3(grid_for(n, T / WAVE)), dim3(T), 0, stream, x);
@@ -1473,8 +1479,14 @@ hoStatus hoTrussHIndex(const uint32_t* row_ptr, const uint32_t* col_idx, uint32_
     x.hist1 = (sweeps == 0 || (uint64_t)prev_changed * 4 > prev_evals) ? 1u : 0u;
     hipLaunchKernelGGL(k_fill32, dim3(1), dim3(64), 0, stream, x.ctr, (size_t)4, 0u);
     if (x.track) {
-      hipLaunchKernelGGL(k_fill64, dim3(grid_for(n, T)), dim3(T), 0, stream, x.dmask, (size_t)n,
-                         (uint64_t)0);
+      // Lemma 4 mode: the masks the previous sweep's changes left are read
+      // now, and this sweep's crossings start empty
+      if (x.lemma4)
+        hipLaunchKernelGGL(k_fill32, dim3(grid_for(2 * (size_t)n, T)), dim3(T), 0, stream,
+                           x.cmask, 2 * (size_t)n, 0u);
+      else
+        hipLaunchKernelGGL(k_fill64, dim3(grid_for(n, T)), dim3(T), 0, stream, x.dmask,
+                           (size_t)n, (uint64_t)0);
       hipLaunchKernelGGL(k_fill32, dim3(grid_for(n, T)), dim3(T), 0, stream, x.tmin, (size_t)n,
                          0xffffffffu);
     }
@@ -1489,7 +1501,7 @@ hoStatus hoTrussHIndex(const uint32_t* row_ptr, const uint32_t* col_idx, uint32_
                              vlo, vhi);
           if (x.h == 2) {
             hipLaunchKernelGGL(k_hx_split, dim3(num_cu() * 8), dim3(T), 0, stream, x);
-            if (x.track)
+            if (x.track && !x.lemma4)
               hipLaunchKernelGGL(k_hx_split_mask, dim3(num_cu() * 2), dim3(T), 0, stream, x);
           }
         }));

@@ -33,6 +33,14 @@
 // values never rise.  So after the first sweep an edge is re-evaluated only if
 // the bucket of c is marked in either endpoint's mask.
 //
+// The default rule is the paper's pruning (Section 4.3, Lemma 4): the same
+// crossing test on edge values instead of path keys.  A changed edge (a -> b)
+// marks the buckets of b+1 .. a at both endpoints; a vertex's mask for the
+// next sweep is the OR over its closed (h-1)-ball, i.e. over every edge its
+// path keys read; an edge is skipped unless c's bucket is marked (cases i-iii
+// of the lemma all leave the bucket of c unmarked).  It re-evaluates a few
+// more edges than the path-key rule but needs no previous keys.
+//
 // Asynchronous sweeps split the vertices into consecutive chunks processed in
 // order; chunk c rebuilds its rows from the keys as they stand (including the
 // ones earlier chunks of the same sweep changed) and then updates the edges
@@ -76,6 +84,8 @@ struct Hx {
   uint32_t* ctr;       // counters: changed, evaluated, rows built, tlist length
   uint32_t track;      // change tracking on: skip clean rows and edges
   uint32_t first;      // first sweep: every edge is evaluated
+  uint32_t lemma4;     // edge masks from changed edge values (Lemma 4), not from path keys
+  uint32_t* cmask;     // Lemma 4: value buckets crossed by changed edges at x, as 2 u32 [2n]
   uint32_t hist1;      // the counting pass also fills the first histogram
   uint32_t* tmin;      // smallest new value among the changed edges at x this sweep [n]
   // h = 2: rows whose relaxations are split over workgroups, {rows, slices} in
@@ -92,6 +102,12 @@ __device__ __forceinline__ uint32_t hx_bucket(uint32_t v) {
   if (v < 32) return v;
   const uint32_t e = 31u - (uint32_t)__clz(v);
   return min(63u, 32u + (e - 5) * 2 + ((v >> (e - 1)) & 1u));
+}
+
+// Buckets of the thresholds c with b < c <= a (a value that fell from a to b).
+__device__ __forceinline__ unsigned long long hx_range_mask(uint32_t b, uint32_t a) {
+  const uint32_t lo = hx_bucket(b + 1), hi = hx_bucket(a);
+  return (~0ull >> (63 - hi)) & ~((1ull << lo) - 1);
 }
 
 __device__ __forceinline__ uint32_t hx_rank(const Hx& x, uint32_t u, uint32_t w) {
@@ -210,10 +226,7 @@ __device__ void hx_row_mask(const Hx& x, uint32_t u, const uint32_t* old, const 
   unsigned long long mk = 0;
   for (uint32_t i = threadIdx.x; i < len; i += blockDim.x) {
     const uint32_t a = old[i], b = fin[i];
-    if (b < a) {
-      const uint32_t lo = hx_bucket(b + 1), hi = hx_bucket(a);
-      mk |= (~0ull >> (63 - hi)) & ~((1ull << lo) - 1);
-    }
+    if (b < a) mk |= hx_range_mask(b, a);
   }
   if ((uint32_t)mk) atomicOr(&s_mask[0], (uint32_t)mk);
   if (mk >> 32) atomicOr(&s_mask[1], (uint32_t)(mk >> 32));
@@ -243,7 +256,7 @@ __global__ void __launch_bounds__(256) k_hx_paths(Hx x, uint32_t vlo, uint32_t v
     uint32_t* old = x.Pold + base;
     if (threadIdx.x == 0) s_rs = 0;
     for (uint32_t i = threadIdx.x; i < len; i += blockDim.x) {
-      if (x.track) old[i] = fin[i];
+      if (x.track && !x.lemma4) old[i] = fin[i];
       row[i] = 0;
     }
     __syncthreads();
@@ -323,7 +336,7 @@ __global__ void __launch_bounds__(256) k_hx_paths(Hx x, uint32_t vlo, uint32_t v
       }
       cur ^= 1u;
     }
-    if (x.track) hx_row_mask(x, u, old, fin, len, s_mask);
+    if (x.track && !x.lemma4) hx_row_mask(x, u, old, fin, len, s_mask);
   }
   if (threadIdx.x == 0 && built) {
     atomicAdd(&x.ctr[HX_CTR_ROWS], built);
@@ -493,6 +506,13 @@ __global__ void __launch_bounds__(256) k_hx_edges(Hx x, uint32_t chunk, uint32_t
       x.touched[v] = 1;
       atomicMin(&x.tmin[u], y);
       atomicMin(&x.tmin[v], y);
+      if (x.lemma4) {
+        const unsigned long long mk = hx_range_mask(y, c);
+        for (uint32_t z : {u, v}) {
+          if ((uint32_t)mk) atomicOr(&x.cmask[2 * z], (uint32_t)mk);
+          if (mk >> 32) atomicOr(&x.cmask[2 * z + 1], (uint32_t)(mk >> 32));
+        }
+      }
     }
     ++changes;
   }
@@ -559,6 +579,39 @@ __global__ void __launch_bounds__(256) k_hx_dirty(Hx x) {
       hit = __ballot(hit) != 0;
     }
     if (lane == 0) x.dirty[r] = hit ? 1u : 0u;
+    if (x.lemma4) {
+      // OR of the crossing masks over the closed (h-1)-ball of r
+      const uint32_t* cm = x.cmask;
+      uint32_t lo = 0, hi = 0;
+      if (lane == 0) {
+        lo = cm[2 * r];
+        hi = cm[2 * r + 1];
+      }
+      if (x.h == 2) {
+        for (uint32_t q = x.rp[r] + lane; q < x.rp[r + 1]; q += WAVE) {
+          const uint32_t y = x.ci[q];
+          lo |= cm[2 * y];
+          hi |= cm[2 * y + 1];
+        }
+      } else if (x.h >= 3 && nt) {
+        const uint64_t* Lr = x.L[x.h - 1] + (size_t)r * x.W;
+        for (uint32_t t = lane; t < nt; t += WAVE) {
+          const uint32_t i = x.tlist[t];
+          uint64_t b = Lr[i] & x.tbits[i];
+          while (b) {
+            const uint32_t y = i * 64 + (uint32_t)__ffsll((long long)b) - 1;
+            lo |= cm[2 * y];
+            hi |= cm[2 * y + 1];
+            b &= b - 1;
+          }
+        }
+      }
+      for (int o = WAVE / 2; o > 0; o >>= 1) {
+        lo |= (uint32_t)__shfl_xor(lo, o, WAVE);
+        hi |= (uint32_t)__shfl_xor(hi, o, WAVE);
+      }
+      if (lane == 0) x.dmask[r] = (uint64_t)hi << 32 | lo;
+    }
   }
 }
 

@@ -138,7 +138,7 @@ def test_hindex_argument_errors_return_before_device_work(ht):
     args = lambda h, flags, ws_bytes, sweeps=C.byref(sw): (  # noqa: E731
         fake, fake, 10, 5, h, flags, 0, fake, sweeps, fake, ws_bytes, C.byref(need), nul)
     assert lib.hoTrussHIndex(*args(0, 0, 1 << 30)) == -1          # h == 0
-    assert lib.hoTrussHIndex(*args(2, 8, 1 << 30)) == -1          # unknown flag
+    assert lib.hoTrussHIndex(*args(2, 16, 1 << 30)) == -1         # unknown flag
     assert lib.hoTrussHIndex(*args(2, 0, 1 << 30, None)) == -1    # no sweep count
     # workspace below the minimum: HO_ERR_WORKSPACE and the minimum reported
     assert lib.hoTrussHIndex(*args(2, 0, 16)) == -3

@@ -14,8 +14,9 @@ from oracle.hindex import hindex_sequence
 pytestmark = pytest.mark.gpu
 
 MODES = [dict(asynchronous=False, track=True), dict(asynchronous=False, track=False),
-         dict(asynchronous=True, track=True), dict(asynchronous=True, track=False)]
-MODE_IDS = ["sync", "sync-all", "async", "async-all"]
+         dict(asynchronous=True, track=True), dict(asynchronous=True, track=False),
+         dict(asynchronous=False, pruning="keys"), dict(asynchronous=True, pruning="keys")]
+MODE_IDS = ["sync", "sync-all", "async", "async-all", "sync-keys", "async-keys"]
 
 
 def run(g, h, **kw):
@@ -29,14 +30,15 @@ def run(g, h, **kw):
 def test_sync_sequence_matches_oracle(seed, h):
     g = W.d1(seed)
     seq = hindex_sequence(g, h)
-    for track in (True, False):
-        t, sweeps = run(g, h, track=track)
+    for kw in (dict(track=True), dict(track=False), dict(pruning="keys")):
+        t, sweeps = run(g, h, **kw)
         assert sweeps == len(seq) - 1
         assert np.array_equal(t.astype(np.int64), seq[-1] + 2)
     for s in range(1, len(seq)):
-        t, sweeps = run(g, h, max_sweeps=s)
-        assert sweeps == s
-        assert np.array_equal(t.astype(np.int64), seq[s] + 2), f"sweep {s}"
+        for kw in (dict(), dict(pruning="keys")):
+            t, sweeps = run(g, h, max_sweeps=s, **kw)
+            assert sweeps == s
+            assert np.array_equal(t.astype(np.int64), seq[s] + 2), f"sweep {s} {kw}"
 
 
 @pytest.mark.parametrize("mode", MODES, ids=MODE_IDS)
