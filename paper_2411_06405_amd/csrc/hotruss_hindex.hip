@@ -52,6 +52,7 @@ namespace hotruss {
 constexpr uint32_t HX_SRC = 1024;   // relaxation sources staged per batch
 constexpr uint32_t HX_BIG = 16384;  // h = 2: rows with more relaxations are split
 constexpr uint32_t HX_SLICE = 64;   // sources per slice of a split row
+constexpr uint32_t HX_BINS = 4 * 64;  // histogram bins per wave (4 per lane)
 constexpr uint32_t HX_STAGE_WORDS = HX_SRC / 64;
 constexpr uint32_t HX_CTR_CHANGED = 0, HX_CTR_EVALS = 1, HX_CTR_ROWS = 2, HX_CTR_TLIST = 3;
 // work counters of the stats mode
@@ -432,12 +433,12 @@ __device__ __forceinline__ uint32_t hx_common(const Hx& x, uint32_t u, uint32_t 
 // Update the edges of chunk `chunk` (ord[cbound[chunk] .. cbound[chunk+1]))
 // or, when ord is not used, every edge; one wave per edge.  The new value is the largest y <= H(e)
 // with at least y common members keyed >= y: one pass counts the members
-// keyed >= H(e) (enough when H(e) stands); otherwise passes with a 64-bin
-// histogram narrow [lo, hi) by 64x each until one value is left.  When most
+// keyed >= H(e) (enough when H(e) stands); otherwise passes with a 256-bin
+// histogram narrow [lo, hi) by 256x each until one value is left.  When most
 // edges are expected to change (hist1), the counting pass fills the first
 // histogram as well.
 __global__ void __launch_bounds__(256) k_hx_edges(Hx x, uint32_t chunk, uint32_t use_ord) {
-  __shared__ uint32_t s_hist[256 / WAVE][WAVE];
+  __shared__ uint32_t s_hist[256 / WAVE][HX_BINS];
   const uint32_t lane = lane_id(), wv = threadIdx.x / WAVE, wpb = blockDim.x / WAVE;
   uint32_t* hist = s_hist[wv];
   uint32_t evals = 0, changes = 0;
@@ -455,9 +456,9 @@ __global__ void __launch_bounds__(256) k_hx_edges(Hx x, uint32_t chunk, uint32_t
     bool counted = false;
     while (true) {
       const bool histo = counted || x.hist1;
-      const uint32_t s = (hi - lo + WAVE - 1) / WAVE;
+      const uint32_t s = (hi - lo + HX_BINS - 1) / HX_BINS;
       if (histo) {
-        hist[lane] = 0;
+        for (uint32_t k = 0; k < 4; ++k) hist[4 * lane + k] = 0;
         __threadfence_block();
       }
       uint32_t ge = 0, seen = 0;
@@ -479,22 +480,38 @@ __global__ void __launch_bounds__(256) k_hx_edges(Hx x, uint32_t chunk, uint32_t
         if (!histo) continue;
       }
       __threadfence_block();
-      const uint32_t hc = hist[lane];
-      uint32_t suf = hc;  // members in bins lane..63
+      // lane l holds bins 4l .. 4l+3; bin j starts at lo + j*s
+      uint32_t hk[4], tot = 0;
+      for (uint32_t k = 0; k < 4; ++k) {
+        hk[k] = hist[4 * lane + k];
+        tot += hk[k];
+      }
+      uint32_t suf = tot;  // members in bins 4*lane .. 255
       for (int o = 1; o < WAVE; o <<= 1) {
         const uint32_t t = __shfl_down(suf, o, WAVE);
         if (lane + o < WAVE) suf += t;
       }
-      const uint32_t bnd = lo + lane * s;
-      const bool ok = bnd < hi && above + suf >= bnd;
-      const uint64_t mask = __ballot(ok);  // lane 0 (bnd = lo) always holds
-      const uint32_t b = 63u - (uint32_t)__clzll(mask);
-      const uint32_t nlo = lo + b * s;
+      // the highest bin whose start is feasible: count(>= start) >= start
+      int best = -1;
+      uint32_t best_cum = 0, best_h = 0, under = 0;
+      for (uint32_t k = 0; k < 4; ++k) {
+        const uint32_t bnd = lo + (4 * lane + k) * s, cum = above + suf - under;
+        if (bnd < hi && cum >= bnd) {
+          best = (int)k;
+          best_cum = cum;
+          best_h = hk[k];
+        }
+        under += hk[k];
+      }
+      const uint64_t mask = __ballot(best >= 0);  // lane 0's first bin (start lo) holds
+      const uint32_t bl = 63u - (uint32_t)__clzll(mask);
+      const uint32_t j = 4 * bl + (uint32_t)__shfl(best, bl, WAVE);
+      const uint32_t nlo = lo + j * s;
       if (s == 1) {
         y = nlo;
         break;
       }
-      above += __shfl(suf, b, WAVE) - __shfl(hc, b, WAVE);
+      above = __shfl(best_cum, bl, WAVE) - __shfl(best_h, bl, WAVE);
       hi = min(nlo + s, hi);
       lo = nlo;
       __threadfence_block();
