@@ -128,22 +128,24 @@ def cpu_baseline(workload: str):
 
 # Algorithmic bytes of the H-index kernels, per unit of counted work:
 #   edge updates: per edge and sweep its endpoints, H and the two drop masks
-#     (28 B); per pass over a common neighbourhood the two ball rows (2 W
-#     words of 8 B); per word with common members the two rank words (8 B);
-#     per common member the two path keys (8 B)
+#     (28 B); the bytes the kernel counts for its passes over common
+#     neighbourhoods (list walk: 12 B per member of the smaller ball -- its id,
+#     key and the probed ball word -- plus 4 B per common member for the rank
+#     word; bitset scan: 16 B per word pair plus 8 B of rank words per word
+#     with common members); per common member the two path keys (8 B)
 #   path-key rows: per row 12 B (offsets, flag); per row entry 4 B (zeroed);
 #     per direct key 24 B (col_idx, edge id, H, rank word and ball word, key);
 #     per relaxation 28 B (the same plus the atomic maximum)
 HX_WORK_KINDS = ("edge_evaluations", "rows_built", "relaxations", "direct_keys",
-                 "row_entries", "passes", "words_with_common", "common_members")
+                 "row_entries", "passes", "scan_bytes", "common_members")
 HX_CPU_SAMPLE_N = 2000  # Chung-Lu sample the H-index oracle finishes in about 10-30 s
 
 
-def _hx_roofline(st: dict, words: int, m: int) -> dict:
+def _hx_roofline(st: dict, m: int) -> dict:
     km = list(st["kernel_ms"].values())
     kl = list(st["kernel_launches"].values())
     w = list(st["work"].values())
-    edge_bytes = w[5] * 2 * words * 8 + w[6] * 8 + w[7] * 8 + st["rounds"] * m * 28
+    edge_bytes = w[6] + w[7] * 8 + st["rounds"] * m * 28
     path_bytes = w[1] * 12 + w[4] * 4 + w[3] * 24 + w[2] * 28
     kinds = {"k_hx_paths": (km[1], kl[1], path_bytes), "k_hx_edges": (km[2], kl[2], edge_bytes)}
     dom = max(kinds, key=lambda k: kinds[k][0])
@@ -226,7 +228,6 @@ def run_hindex(args) -> dict:
     st = ht.last_stats()
     if args.calibrate:
         _calibration_copy(torch, dev)
-    words = ((g.n + 63) // 64 + 7) // 8 * 8
     line = {
         "metric": f"edges/s to h-trussness (h={h})", "value": g.m * args.steps / dt,
         "unit": "edges/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
@@ -238,7 +239,7 @@ def run_hindex(args) -> dict:
                    "peeling_ms": peel_ms, "other_modes": modes,
                    "value_changes": int(st["events"]),
                    "work": dict(zip(HX_WORK_KINDS, map(int, st["work"].values())))},
-        "roofline": _hx_roofline(st, words, g.m),
+        "roofline": _hx_roofline(st, g.m),
     }
     if not args.no_cpu_baseline:
         gs = W.d2(n=HX_CPU_SAMPLE_N)

@@ -260,7 +260,7 @@ hoStatus hoTrussComponents(const uint32_t *row_ptr, const uint32_t *col_idx, uin
  *               the h-hop balls, known only on the device: pass at least
  *               hoTrussHIndexWorkspaceBytes(n, m, h) bytes; when the balls
  *               need more, the call returns HO_ERR_WORKSPACE with
- *               *needed_bytes set (4 bytes per ball member, 8 for h >= 3, and
+ *               *needed_bytes set (8 bytes per ball member, 12 for h >= 3, and
  *               4 more with HO_HINDEX_KEYS, on top of the minimum); call again
  *               with that much.  On success
  *               *needed_bytes (if not NULL) is the size this graph needed.
@@ -270,8 +270,9 @@ hoStatus hoTrussComponents(const uint32_t *row_ptr, const uint32_t *col_idx, uin
  *   device_ms = the whole call.  HO_HINDEX_STATS adds kernel_ms/kernel_launches
  *   [0] balls, H^(0) and ranks, [1] path-key rows, [2] edge updates, [3] change
  *   tracking, and work [2] relaxations, [3] direct keys, [4] row entries
- *   written, [5] passes over a common neighbourhood, [6] words with common
- *   members visited, [7] common members visited. */
+ *   written, [5] passes over a common neighbourhood, [6] bytes those passes
+ *   read (ball rows, rank words, member lists; keys excluded), [7] common
+ *   members visited. */
 #define HO_HINDEX_ASYNC 0x1u
 #define HO_HINDEX_ALL 0x2u
 #define HO_HINDEX_STATS 0x4u

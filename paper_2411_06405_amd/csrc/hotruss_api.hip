@@ -1442,13 +1442,18 @@ hoStatus hoTrussHIndex(const uint32_t* row_ptr, const uint32_t* col_idx, uint32_
   HIPCHK(hipStreamSynchronize(stream));
   // P[0], P[1] (h >= 3), previous keys (path-key pruning only)
   const bool keys = !(flags & HO_HINDEX_ALL) && (flags & HO_HINDEX_KEYS);
-  const uint32_t nbuf = (d.h >= 3 ? 2 : 1) + (keys ? 1 : 0);
+  // plus the member lists
+  const uint32_t nbuf = (d.h >= 3 ? 2 : 1) + (keys ? 1 : 0) + 1;
   const size_t need = q.base + nbuf * hx_key_bytes(members) + ALIGN;
   if (needed_bytes) *needed_bytes = need;
   if (workspace_bytes < need) return HO_ERR_WORKSPACE;
   x.P[0] = (uint32_t*)at(q.base);
   x.P[1] = d.h >= 3 ? (uint32_t*)at(q.base + hx_key_bytes(members)) : nullptr;
-  x.Pold = keys ? (uint32_t*)at(q.base + (nbuf - 1) * hx_key_bytes(members)) : nullptr;
+  x.Pold = keys ? (uint32_t*)at(q.base + (nbuf - 2) * hx_key_bytes(members)) : nullptr;
+  x.mem = (uint32_t*)at(q.base + (nbuf - 1) * hx_key_bytes(members));
+  HOCHK(timed(0, [&] {
+    hipLaunchKernelGGL(k_hx_members, dim3(grid_for(n, T / WAVE)), dim3(T), 0, stream, x);
+  }));
   x.dmask = (uint64_t*)at(q.off_dmask);
   x.tmin = (uint32_t*)at(q.off_tmin);
   x.bigctr = (unsigned long long*)at(q.off_bigctr);
@@ -1557,7 +1562,7 @@ hoStatus hoTrussHIndex(const uint32_t* row_ptr, const uint32_t* col_idx, uint32_
     t_stats.work[3] = st8[HX_ST_DIRECT];
     t_stats.work[4] = st8[HX_ST_ENTRIES];
     t_stats.work[5] = st8[HX_ST_PASSES];
-    t_stats.work[6] = st8[HX_ST_WORDS];
+    t_stats.work[6] = st8[HX_ST_SCAN];
     t_stats.work[7] = st8[HX_ST_MEMBERS];
   }
   *out_sweeps = sweeps;

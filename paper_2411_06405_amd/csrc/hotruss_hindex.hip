@@ -19,6 +19,8 @@
 // vertex order: the key of w is at P[boff[x] + rank_x(w)], with
 //     rank_x(w) = wp[x*W + w/64] + popcount(L[h](x) word w/64 below bit w),
 // wp holding, per row and word, the members in the row's earlier words.
+// The members themselves are listed in the same order (mem), so the key of
+// the i-th member of x's ball is P[boff[x] + i].
 // A key of 0 also stands for "not reached yet": a path key is never below
 // 0, so the placeholder can only lose a maximum.
 //
@@ -56,7 +58,7 @@ constexpr uint32_t HX_BINS = 4 * 64;  // histogram bins per wave (4 per lane)
 constexpr uint32_t HX_STAGE_WORDS = HX_SRC / 64;
 constexpr uint32_t HX_CTR_CHANGED = 0, HX_CTR_EVALS = 1, HX_CTR_ROWS = 2, HX_CTR_TLIST = 3;
 // work counters of the stats mode
-constexpr uint32_t HX_ST_PASSES = 0, HX_ST_WORDS = 1, HX_ST_MEMBERS = 2, HX_ST_ROWS = 3,
+constexpr uint32_t HX_ST_PASSES = 0, HX_ST_SCAN = 1, HX_ST_MEMBERS = 2, HX_ST_ROWS = 3,
                    HX_ST_DIRECT = 4, HX_ST_RELAX = 5, HX_ST_ENTRIES = 6, HX_ST_EVALS = 7;
 
 struct Hx {
@@ -70,6 +72,7 @@ struct Hx {
   const uint64_t* L[HMAX + 1];  // closed balls of G, n rows of W words
   uint32_t n, m, h, W;
   uint32_t* wp;        // per row and word: members of L[h] in earlier words [n*W]
+  uint32_t* mem;       // the members of L[h](x) in increasing order, row x at boff[x] [S]
   uint32_t* cnt;       // |L[h](x)| [n]
   uint64_t* boff;      // start of row x's path keys [n+1]
   uint32_t* H;         // current H-index of every edge [m]
@@ -158,6 +161,27 @@ __global__ void __launch_bounds__(1024) k_hx_scan(const uint32_t* __restrict__ c
     run += cnt[i];
   }
   if (t == 1023) off[n] = s[1023];
+}
+
+// Member lists of every ball, in vertex order (one wave per row).
+__global__ void __launch_bounds__(256) k_hx_members(Hx x) {
+  const uint32_t lane = lane_id(), wpb = blockDim.x / WAVE;
+  const uint64_t* Lh = x.L[x.h];
+  for (uint32_t r = blockIdx.x * wpb + threadIdx.x / WAVE; r < x.n; r += gridDim.x * wpb) {
+    uint32_t* out = x.mem + x.boff[r];
+    uint32_t run = 0;
+    for (uint32_t i0 = 0; i0 < x.W; i0 += WAVE) {
+      const uint32_t i = i0 + lane;
+      uint64_t b = i < x.W ? Lh[(size_t)r * x.W + i] : 0;
+      uint32_t tot;
+      uint32_t at = run + wave_excl_scan((uint32_t)__popcll(b), &tot);
+      while (b) {
+        out[at++] = i * 64 + (uint32_t)__ffsll((long long)b) - 1;
+        b &= b - 1;
+      }
+      run += tot;
+    }
+  }
 }
 
 // Edge ids in order of their upper endpoint: row x's lower slots (its first
@@ -390,30 +414,69 @@ __global__ void __launch_bounds__(256) k_hx_split_mask(Hx x) {
 }
 
 // f(min(P(u,w), P(v,w))) for every common member w != u, v of the two balls
-// (all 64 lanes call; lanes take consecutive words).  Every HX_STOP_EVERY
-// word rows, at a point all lanes reach together, stop() may end the scan.
-// Returns the number of words with common members this lane visited.
+// (all 64 lanes call).  Two ways, chosen per edge:
+//   list:   walk the member list of the smaller ball (its keys are aligned
+//           with it) and test each member in the other ball's bitset row,
+//           taking that key through the rank words.  Lanes share the work
+//           evenly, and consecutive edges share an endpoint whose rows stay
+//           cached, so little more than the list and its keys come from HBM.
+//   bitset: AND the two rows word by word, lanes on consecutive words (used
+//           when both balls are large, where the rows are cheaper than lists).
+// Every HX_STOP_EVERY steps, at a point all lanes reach together, stop() may
+// end the scan.  Returns the algorithmic bytes this lane read, keys excluded.
 constexpr uint32_t HX_STOP_EVERY = 4;
 
 template <class F, class S>
-__device__ __forceinline__ uint32_t hx_common(const Hx& x, uint32_t u, uint32_t v, F&& f,
-                                              S&& stop) {
+__device__ __forceinline__ unsigned long long hx_common(const Hx& x, uint32_t u, uint32_t v,
+                                                        F&& f, S&& stop) {
+  const uint32_t cu = x.cnt[u], cv = x.cnt[v];
+  unsigned long long bytes = 0;
+  uint32_t it = 0;
+  if (min(cu, cv) < 2 * x.W) {
+    const uint32_t a = cu <= cv ? u : v, b = cu <= cv ? v : u;  // walk a, probe b
+    const uint32_t na = min(cu, cv);
+    const uint32_t* Ma = x.mem + x.boff[a];
+    const uint32_t* Pa = x.P[0] + x.boff[a];
+    const uint32_t* Pb = x.P[0] + x.boff[b];
+    const uint64_t* Lb = x.L[x.h] + (size_t)b * x.W;
+    const uint32_t* Wb = x.wp + (size_t)b * x.W;
+    for (uint32_t i0 = 0; i0 < na; i0 += WAVE) {
+      const uint32_t i = i0 + lane_id();
+      if (i < na) {
+        const uint32_t w = Ma[i];
+        bytes += 12;
+        if (w != u && w != v) {
+          const uint64_t word = Lb[w >> 6];
+          if ((word >> (w & 63)) & 1ull) {
+            bytes += 4;
+            const uint32_t rb = Wb[w >> 6] + (uint32_t)__popcll(word & ((1ull << (w & 63)) - 1));
+            f(min(Pa[i], Pb[rb]));
+          }
+        }
+      }
+      if (++it == HX_STOP_EVERY) {
+        it = 0;
+        if (stop()) break;
+      }
+    }
+    return bytes;
+  }
   const uint64_t* Lu = x.L[x.h] + (size_t)u * x.W;
   const uint64_t* Lv = x.L[x.h] + (size_t)v * x.W;
   const uint32_t* Wu = x.wp + (size_t)u * x.W;
   const uint32_t* Wv = x.wp + (size_t)v * x.W;
   const uint32_t* Pu = x.P[0] + x.boff[u];
   const uint32_t* Pv = x.P[0] + x.boff[v];
-  uint32_t words = 0, it = 0;
   for (uint32_t i0 = 0; i0 < x.W; i0 += WAVE) {
     const uint32_t i = i0 + lane_id();
     if (i < x.W) {
       const uint64_t a = Lu[i], b = Lv[i];
+      bytes += 16;
       uint64_t c = a & b;
       if (i == (u >> 6)) c &= ~(1ull << (u & 63));
       if (i == (v >> 6)) c &= ~(1ull << (v & 63));
       if (c) {
-        ++words;
+        bytes += 8;
         const uint32_t ra = Wu[i], rb = Wv[i];
         do {
           const uint64_t below = (c & (~c + 1)) - 1;  // bits under the lowest set bit
@@ -427,7 +490,7 @@ __device__ __forceinline__ uint32_t hx_common(const Hx& x, uint32_t u, uint32_t 
       if (stop()) break;
     }
   }
-  return words;
+  return bytes;
 }
 
 // Update the edges of chunk `chunk` (ord[cbound[chunk] .. cbound[chunk+1]))
@@ -442,7 +505,7 @@ __global__ void __launch_bounds__(256) k_hx_edges(Hx x, uint32_t chunk, uint32_t
   const uint32_t lane = lane_id(), wv = threadIdx.x / WAVE, wpb = blockDim.x / WAVE;
   uint32_t* hist = s_hist[wv];
   uint32_t evals = 0, changes = 0;
-  unsigned long long passes = 0, words = 0, members = 0;  // stats mode (per lane)
+  unsigned long long passes = 0, scan = 0, members = 0;  // stats mode (per lane)
   const uint32_t klo = use_ord ? x.cbound[chunk] : 0, khi = use_ord ? x.cbound[chunk + 1] : x.m;
   for (uint32_t k = klo + blockIdx.x * wpb + wv; k < khi; k += gridDim.x * wpb) {
     const uint32_t e = use_ord ? x.ord[k] : k;
@@ -464,7 +527,7 @@ __global__ void __launch_bounds__(256) k_hx_edges(Hx x, uint32_t chunk, uint32_t
       uint32_t ge = 0, seen = 0;
       ++passes;
       // the counting pass may stop as soon as c members are keyed >= c
-      words += hx_common(
+      scan += hx_common(
           x, u, v,
           [&](uint32_t val) {
             ++seen;
@@ -538,12 +601,14 @@ __global__ void __launch_bounds__(256) k_hx_edges(Hx x, uint32_t chunk, uint32_t
     if (changes) atomicAdd(&x.ctr[HX_CTR_CHANGED], changes);
   }
   if (x.stat) {
-    words = wave_sum((uint32_t)words);
-    members = wave_sum((uint32_t)members);
+    for (int o = WAVE / 2; o > 0; o >>= 1) {
+      scan += __shfl_xor(scan, o, WAVE);
+      members += __shfl_xor(members, o, WAVE);
+    }
     if (lane == 0 && evals) {
       atomicAdd(&x.stat[HX_ST_EVALS], (unsigned long long)evals);
       atomicAdd(&x.stat[HX_ST_PASSES], passes);
-      atomicAdd(&x.stat[HX_ST_WORDS], words);
+      atomicAdd(&x.stat[HX_ST_SCAN], scan);
       atomicAdd(&x.stat[HX_ST_MEMBERS], members);
     }
   }
