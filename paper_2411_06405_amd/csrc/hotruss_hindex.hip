@@ -500,7 +500,7 @@ __device__ __forceinline__ unsigned long long hx_common(const Hx& x, uint32_t u,
 // histogram narrow [lo, hi) by 256x each until one value is left.  When most
 // edges are expected to change (hist1), the counting pass fills the first
 // histogram as well.
-__global__ void __launch_bounds__(256) k_hx_edges(Hx x, uint32_t chunk, uint32_t use_ord) {
+__global__ void __launch_bounds__(256, 5) k_hx_edges(Hx x, uint32_t chunk, uint32_t use_ord) {
   __shared__ uint32_t s_hist[256 / WAVE][HX_BINS];
   const uint32_t lane = lane_id(), wv = threadIdx.x / WAVE, wpb = blockDim.x / WAVE;
   uint32_t* hist = s_hist[wv];
