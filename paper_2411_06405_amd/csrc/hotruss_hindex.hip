@@ -53,7 +53,7 @@ namespace hotruss {
 
 constexpr uint32_t HX_SRC = 1024;   // relaxation sources staged per batch
 constexpr uint32_t HX_BIG = 16384;  // h = 2: rows with more relaxations are split
-constexpr uint32_t HX_SLICE = 64;   // sources per slice of a split row
+constexpr uint32_t HX_SLICE = 16;   // sources per slice of a split row
 constexpr uint32_t HX_BINS = 4 * 64;  // histogram bins per wave (4 per lane)
 constexpr uint32_t HX_STAGE_WORDS = HX_SRC / 64;
 constexpr uint32_t HX_CTR_CHANGED = 0, HX_CTR_EVALS = 1, HX_CTR_ROWS = 2, HX_CTR_TLIST = 3;
