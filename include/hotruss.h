@@ -255,7 +255,8 @@ hoStatus hoTrussComponents(const uint32_t *row_ptr, const uint32_t *col_idx, uin
  *               else stop after that many sweeps.  out_trussness then holds
  *               H + 2 of the last sweep (synchronous: H^(max_sweeps) + 2).
  *   out_trussness  device [m]: H + 2 per canonical edge id.
- *   out_sweeps  host: sweeps run.
+ *   out_sweeps  host: sweeps run.  The call waits on `stream` once per sweep
+ *               (to read how many values changed) and returns when done.
  *   workspace   device, caller-owned.  Its size depends on the total size of
  *               the h-hop balls, known only on the device: pass at least
  *               hoTrussHIndexWorkspaceBytes(n, m, h) bytes; when the balls
