@@ -490,7 +490,7 @@ def main(argv=None):
     args = ap.parse_args(argv)
     if args.gpus != 1:
         print(json.dumps({"error": "this benchmark runs on exactly one GPU; "
-                                   "multi-GPU runs are not part of this build"}))
+                                   "this library runs on one GPU"}))
         return 2
 
     if args.workload == "batched":
