@@ -489,8 +489,8 @@ def main(argv=None):
                     help="also copy a 256 MiB buffer (reference kernel for HBM counters)")
     args = ap.parse_args(argv)
     if args.gpus != 1:
-        print(json.dumps({"error": "this benchmark runs on exactly one GPU; "
-                                   "this library runs on one GPU"}))
+        print(json.dumps({"error": "this benchmark runs on exactly one GPU (--gpus 1); "
+                                   "the library has no multi-GPU path"}))
         return 2
 
     if args.workload == "batched":
