@@ -21,6 +21,9 @@ Two more workloads measure the multi-graph forms:
                        Chung-Lu graph: synchronous sweeps timed, asynchronous
                        and recompute-everything sweeps and the peeling method
                        once each, all outputs compared bit for bit
+  --workload hindex_iterations
+                       sweeps to convergence of the synchronous and the
+                       asynchronous H-index iteration on several graphs
 
 Prints one JSON line.  Only one GPU is used; --gpus above 1 exits with a
 message.
@@ -162,6 +165,43 @@ def _hx_roofline(st: dict, m: int) -> dict:
             "share_of_device_time": ms / max(sum(km), 1e-9),
             "kernel_ms": {"init": km[0], "k_hx_paths": km[1], "k_hx_edges": km[2],
                           "tracking": km[3]}}
+
+
+def run_hindex_iterations(args) -> dict:
+    """Sweeps to convergence of the synchronous and asynchronous H-index
+    iterations (the comparison of the paper's Fig. 6) on several synthetic
+    graphs; both outputs are compared bit for bit."""
+    import torch
+    import paper_2411_06405_amd as ht
+    cases = [(f"G(200,0.05) seed {s}", W.d1(s), 2) for s in range(3)]
+    cases += [("Chung-Lu n=20000", W.d2(n=20_000), 1), ("Chung-Lu n=20000", W.d2(n=20_000), 2),
+              ("Chung-Lu n=100000", W.d2(), 1), ("Chung-Lu n=100000", W.d2(), 2),
+              ("R-MAT scale 12", W.d3(scale=12), 2), ("R-MAT scale 14", W.d3(scale=14), 1)]
+    rows = []
+    dev = torch.device("cuda:0")
+    for name, g, h in cases:
+        _log(f"{name} h={h} m={g.m}")
+        rp = torch.from_numpy(g.row_ptr.view(np.int32)).to(dev)
+        ci = torch.from_numpy(g.col_idx.view(np.int32)).to(dev)
+        ws = ht.hindex_workspace(rp, ci, g.n, h, device=dev)
+        row = {"graph": name, "n": g.n, "m": g.m, "h": h}
+        outs = []
+        for mode, asyn in (("sync", False), ("async", True)):
+            ht.hindex(rp, ci, g.n, h, asynchronous=asyn, workspace=ws, device=dev)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            t, sw = ht.hindex(rp, ci, g.n, h, asynchronous=asyn, workspace=ws, device=dev)
+            torch.cuda.synchronize()
+            row[f"{mode}_sweeps"] = sw
+            row[f"{mode}_ms"] = (time.perf_counter() - t0) * 1e3
+            outs.append(t)
+        row["identical"] = bool(torch.equal(outs[0], outs[1]))
+        rows.append(row)
+        del ws
+        torch.cuda.empty_cache()
+    return {"metric": "H-index sweeps to convergence, synchronous vs asynchronous",
+            "unit": "sweeps", "n_gpus": 1, "data": "synthetic", "dtype": "u32",
+            "higher_is_better": False, "rows": rows}
 
 
 def _calibration_copy(torch, dev) -> None:
@@ -472,7 +512,8 @@ def main(argv=None):
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="chung_lu_100k_h2",
-                    choices=sorted(WORKLOADS) + ["batched", "serve", "hindex"])
+                    choices=sorted(WORKLOADS) + ["batched", "serve", "hindex",
+                                                 "hindex_iterations"])
     ap.add_argument("--graphs", type=int, default=W.D4_B, help="batched: number of graphs")
     ap.add_argument("--requests", type=int, default=200, help="serve: number of requests")
     ap.add_argument("--max-class", type=int, default=0,
@@ -501,6 +542,9 @@ def main(argv=None):
         return 0
     if args.workload == "hindex":
         print(json.dumps(run_hindex(args)), flush=True)
+        return 0
+    if args.workload == "hindex_iterations":
+        print(json.dumps(run_hindex_iterations(args)), flush=True)
         return 0
 
     import torch
