@@ -150,3 +150,17 @@ def test_hindex_argument_errors_return_before_device_work(ht):
     assert wb(200, 1000, 0) == 0
     assert wb(200, 1000, 1) < wb(200, 1000, 2) < wb(200, 1000, 3)
     assert wb(1000, 5000, 2) > wb(500, 5000, 2)
+
+
+def test_binding_constants_match_the_header(ht):
+    # every HO_* flag the binding passes has the value the header defines
+    text = (ROOT / "include" / "hotruss.h").read_text()
+    defined = {name: int(val, 16) for name, val in
+               re.findall(r"#define\s+(HO_\w+)\s+(0x[0-9a-fA-F]+)u", text)}
+    used = {name: getattr(ht._lib, name) for name in dir(ht._lib)
+            if name.startswith(("HO_FLAG_", "HO_HINDEX_"))}
+    assert used and set(used) <= set(defined)
+    for name, val in used.items():
+        assert defined[name] == val, name
+    enum = dict((name, int(val)) for name, val in re.findall(r"(HO_\w+)\s*=\s*(-?\d+)", text))
+    assert enum["HO_OK"] == ht._lib.HO_OK and enum["HO_ERR_WORKSPACE"] == ht._lib.HO_ERR_WORKSPACE
