@@ -237,6 +237,8 @@ hoStatus hoTrussComponents(const uint32_t *row_ptr, const uint32_t *col_idx, uin
  * where P(x,w) is the largest smallest-H over paths of at most h edges from x
  * to w; the values never rise and stop at t(e, h) - 2.
  *
+ *   row_ptr, col_idx, n, m, h  as for hoTrussDecompose (device CSR of a simple
+ *               undirected graph, symmetric, rows sorted; h >= 1).
  *   flags       0: synchronous sweeps (every update reads the previous
  *               sweep's values; the sequence of the paper's definition).
  *               HO_HINDEX_ASYNC: asynchronous sweeps (vertices in 8 chunks
@@ -249,8 +251,8 @@ hoStatus hoTrussComponents(const uint32_t *row_ptr, const uint32_t *col_idx, uin
  *               reads fell from >= its value to below it).  HO_HINDEX_KEYS:
  *               apply that test to the path keys of its endpoints instead
  *               (finer, but each rebuilt row is compared with its previous
- *               keys; same values).  HO_HINDEX_STATS: time
- *               every launch group with HIP events and count work (slower).
+ *               keys; same values).  HO_HINDEX_STATS: time every launch
+ *               group with HIP events and count work (slower).
  *   max_sweeps  0: run until a sweep changes nothing (that sweep is counted);
  *               else stop after that many sweeps.  out_trussness then holds
  *               H + 2 of the last sweep (synchronous: H^(max_sweeps) + 2).
@@ -263,8 +265,9 @@ hoStatus hoTrussComponents(const uint32_t *row_ptr, const uint32_t *col_idx, uin
  *               need more, the call returns HO_ERR_WORKSPACE with
  *               *needed_bytes set (8 bytes per ball member, 12 for h >= 3, and
  *               4 more with HO_HINDEX_KEYS, on top of the minimum); call again
- *               with that much.  On success
- *               *needed_bytes (if not NULL) is the size this graph needed.
+ *               with that much.
+ *   needed_bytes  host, may be NULL: the workspace size this graph and these
+ *               flags need (set on success and on HO_ERR_WORKSPACE).
  *   Errors as for hoTrussDecompose; flags outside the four bits give
  *   HO_ERR_INVALID_ARG.  hoTrussLastStats afterwards: rounds = sweeps, events =
  *   value changes, work[0] = edge evaluations, work[1] = path-key rows built,
