@@ -216,7 +216,6 @@ def _calibration_copy(torch, dev) -> None:
 def run_hindex(args) -> dict:
     import torch
     import paper_2411_06405_amd as ht
-    from oracle.hindex import hindex_trussness
 
     make, _, desc = WORKLOADS["chung_lu_100k_h2"]
     h = args.hx_h
@@ -282,6 +281,7 @@ def run_hindex(args) -> dict:
         "roofline": _hx_roofline(st, g.m),
     }
     if not args.no_cpu_baseline:
+        from oracle.hindex import hindex_trussness  # the CPU-baseline leg only
         gs = W.d2(n=HX_CPU_SAMPLE_N)
         t1 = time.perf_counter()
         _, sw = hindex_trussness(gs, h)
