@@ -212,6 +212,8 @@ def hindex_workspace(row_ptr, col_idx, n: int, h: int, pruning: str = "lemma4", 
                      device="cuda"):
     """A workspace that fits this graph's H-index run (two calls: the first
     reports the size the balls need)."""
+    if pruning not in ("lemma4", "keys"):
+        raise ValueError("pruning is 'lemma4' (the paper's rule on edge values) or 'keys'")
     rp = _dev_u32(row_ptr, device)
     ci = _dev_u32(col_idx, device)
     m = ci.numel() // 2
@@ -241,14 +243,14 @@ def hindex(row_ptr, col_idx, n: int, h: int, asynchronous: bool = False, track: 
     knows: a first call with the minimum reports the size needed; the
     workspace is then grown and the call repeated.  A caller-given workspace
     that is too small raises."""
+    if pruning not in ("lemma4", "keys"):
+        raise ValueError("pruning is 'lemma4' (the paper's rule on edge values) or 'keys'")
     rp = _dev_u32(row_ptr, device)
     ci = _dev_u32(col_idx, device)
     m = ci.numel() // 2
     out = torch.empty(max(m, 1), dtype=torch.int32, device=device)
     flags = ((HO_HINDEX_ASYNC if asynchronous else 0) | (0 if track else HO_HINDEX_ALL)
              | (HO_HINDEX_STATS if stats else 0) | (HO_HINDEX_KEYS if pruning == "keys" else 0))
-    if pruning not in ("lemma4", "keys"):
-        raise ValueError("pruning is 'lemma4' (the paper's rule on edge values) or 'keys'")
     sweeps = C.c_uint32()
     needed = C.c_size_t()
     grow = workspace is None

@@ -164,3 +164,13 @@ def test_binding_constants_match_the_header(ht):
         assert defined[name] == val, name
     enum = dict((name, int(val)) for name, val in re.findall(r"(HO_\w+)\s*=\s*(-?\d+)", text))
     assert enum["HO_OK"] == ht._lib.HO_OK and enum["HO_ERR_WORKSPACE"] == ht._lib.HO_ERR_WORKSPACE
+
+
+def test_hindex_binding_rejects_unknown_pruning_on_the_host(ht):
+    import numpy as np
+    rp = np.array([0, 1, 2], dtype=np.uint32)
+    ci = np.array([1, 0], dtype=np.uint32)
+    with pytest.raises(ValueError):
+        ht.hindex(rp, ci, 2, 2, pruning="bogus")
+    with pytest.raises(ValueError):
+        ht.hindex_workspace(rp, ci, 2, 2, pruning="bogus")
