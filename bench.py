@@ -1,8 +1,13 @@
 """Benchmark: edges/s to h-trussness on one MI355X.
 
 A step is one full decomposition (every edge's h-trussness) of a synthetic
-graph whose CSR is already resident in HBM.  Default workload: Chung-Lu
-power-law graph, n = 100,000, average degree 10, exponent 2.5, seed 1, h = 2.
+graph whose CSR is already resident in HBM.  Default workload: R-MAT scale 18
+(262,144 vertices, edge factor 16, (a,b,c,d) = (0.57,0.19,0.19,0.05), seed 1),
+symmetrised and deduplicated, h = 2.  `value` is m * K / wall time of the K
+timed decompositions; the line also carries each decomposition's device time
+(HIP events from its first kernel to its completion event) as median, min and
+max.  Other single-graph workloads: chung_lu_100k_h2, rmat18_h3,
+chung_lu_100k_h1, er200_h2.
 
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload NAME]
 
@@ -107,26 +112,55 @@ def roofline_from_stats(st: dict, workload: str):
             "share_of_device_time": km[dom] / max(sum(km.values()), 1e-9)}
 
 
-def cpu_baseline(workload: str):
-    """Time the plain CPU oracle on a bounded sample of the workload family."""
+def cpu_model() -> str:
+    """The host CPU's model name (as lscpu reports it)."""
+    try:
+        for line in Path("/proc/cpuinfo").read_text().splitlines():
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def _time_oracle(g, h, threads):
     import oracle
+    t0 = time.perf_counter()
+    _, _, info = oracle.decompose(g, h, threads=threads)
+    return time.perf_counter() - t0, info
+
+
+def cpu_baseline(workload: str):
+    """Time the plain CPU oracle on bounded samples of the workload family:
+    all host cores on the main sample, and one core next to all cores on a
+    smaller one (the oracle's parallel speed-up on the same input)."""
     make, h, _ = WORKLOADS[workload]
     if workload.startswith("chung_lu"):
-        g = W.d2(n=CPU_SAMPLE_N)
-        desc = f"oracle full decomposition of Chung-Lu n={CPU_SAMPLE_N} (same avg_deg/gamma/seed)"
+        g, g1 = W.d2(n=CPU_SAMPLE_N), W.d2(n=CPU_SAMPLE_N // 2)
+        desc = f"Chung-Lu n={CPU_SAMPLE_N} (same avg_deg/gamma/seed)"
+        desc1 = f"Chung-Lu n={CPU_SAMPLE_N // 2}"
     elif workload.startswith("rmat"):
-        g = W.d3(scale=10)
-        desc = "oracle full decomposition of R-MAT scale 10 (same a,b,c,d, ef, seed)"
+        g, g1 = W.d3(scale=10), W.d3(scale=9)
+        desc = "R-MAT scale 10 (same a,b,c,d, ef, seed)"
+        desc1 = "R-MAT scale 9"
     else:
-        g = make()
-        desc = "oracle full decomposition of the workload itself"
+        g = g1 = make()
+        desc = desc1 = "the workload itself"
     cores = len(os.sched_getaffinity(0))
-    t0 = time.perf_counter()
-    _, _, info = oracle.decompose(g, h, threads=cores)
-    dt = time.perf_counter() - t0
+    dt, info = _time_oracle(g, h, cores)
+    dt1, info1 = _time_oracle(g1, h, 1)
+    dtn, _ = _time_oracle(g1, h, cores)
     return {"value": g.m / dt, "unit": "edges/s", "cores": cores, "kind": "oracle",
-            "sample": f"{desc}: m={g.m}, {info['rounds']} rounds, {dt:.2f} s; the oracle "
-                      f"re-evaluates every live edge each round, so its rate falls as graphs grow"}
+            "cpu_model": cpu_model(),
+            "sample": f"oracle full decomposition of {desc}: m={g.m}, {info['rounds']} rounds, "
+                      f"{dt:.2f} s on {cores} threads; the oracle re-evaluates every live edge "
+                      f"each round, so its rate falls as graphs grow",
+            "one_core": {"value": g1.m / dt1, "unit": "edges/s", "cores": 1,
+                         "sample": f"oracle full decomposition of {desc1}: m={g1.m}, "
+                                   f"{info1['rounds']} rounds, {dt1:.2f} s on 1 thread"},
+            "all_cores_same_sample": {"value": g1.m / dtn, "unit": "edges/s", "cores": cores,
+                                      "seconds": dtn},
+            }
 
 
 # Algorithmic bytes of the H-index kernels, per unit of counted work:
@@ -511,7 +545,7 @@ def main(argv=None):
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="chung_lu_100k_h2",
+    ap.add_argument("--workload", default="rmat18_h2",
                     choices=sorted(WORKLOADS) + ["batched", "serve", "hindex",
                                                  "hindex_iterations"])
     ap.add_argument("--graphs", type=int, default=W.D4_B, help="batched: number of graphs")
@@ -561,14 +595,18 @@ def main(argv=None):
     for _ in range(args.warmup):
         ht.decompose(rp, ci, g.n, h, workspace=ws, device=dev)
     torch.cuda.synchronize()
+    _log(f"{desc}: n={g.n} m={g.m}, timing {args.steps} decompositions")
+    device_ms = []
     t0 = time.perf_counter()
     for _ in range(args.steps):
         t, rho = ht.decompose(rp, ci, g.n, h, workspace=ws, device=dev)
+        device_ms.append(ht.last_stats()["device_ms"])  # the call has completed
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
     st = ht.last_stats()
     ms = dt * 1000.0 / max(args.steps, 1)
     value = g.m * args.steps / dt
+    _log(f"timed: {ms:.1f} ms per decomposition")
     # one more decomposition with every round kernel timed by HIP events on
     # this stream and the chunked kernels' work counted (host-driven rounds)
     ht.decompose(rp, ci, g.n, h, workspace=ws, device=dev, tune=stats_tune)
@@ -584,6 +622,12 @@ def main(argv=None):
                    "rounds": int(st["rounds"]), "levels": int(st["levels"]),
                    "top_level_events": int(st["events"]),
                    "overflow_rounds": int(st["overflows"])},
+        "device_ms": {"median": float(np.median(device_ms)) if device_ms else None,
+                      "min": float(np.min(device_ms)) if device_ms else None,
+                      "max": float(np.max(device_ms)) if device_ms else None,
+                      "runs": len(device_ms)},
+        "edges_per_s_device_median": (g.m / (float(np.median(device_ms)) * 1e-3)
+                                      if device_ms else None),
         "roofline": roofline_from_stats(stt, args.workload),
         "kernel_ms_stats_mode": {k: round(v, 3) for k, v in stt["kernel_ms"].items()},
     }

@@ -26,7 +26,22 @@
  *             workspace and keeps no pointer after the call returns (sessions
  *             excepted, see below).
  *   Streams   work is enqueued on `stream`.  Calls return after the work has
- *             completed on that stream unless stated otherwise.
+ *             completed on that stream unless stated otherwise (hoSubmit is
+ *             host-only).  This is deliberate: the number of peel rounds is
+ *             decided on the device as the rounds run (Algorithm 1 stops when
+ *             S is empty), so the host keeps replaying captured round graphs
+ *             until the device reports that the decomposition has finished,
+ *             and it can only stop once it has seen that report.  Callers that
+ *             need asynchrony use a session (hoSubmit / hoSessionProgress /
+ *             hoPoll) or a host thread per stream.
+ *   Sizes     n <= 524,288 for every entry point that keeps h-hop balls
+ *             (hoTrussHSupport, hoTrussDecompose and its batched and session
+ *             forms, hoTrussHIndex): a ball is a bitset row of ceil(n/64)
+ *             64-bit words, rounded up to a multiple of 8, and each row is
+ *             built in the 64 KiB of LDS one workgroup may use, so at most
+ *             8,192 words.  Larger n gives HO_ERR_INVALID_ARG (and a
+ *             workspace query of 0).  The ball store itself is about
+ *             (2h-1) * n^2 / 8 bytes (h = 2, n = 524,288: 103 GB).
  *   Errors    argument errors return at once, before any device work.  The
  *             CSR is always validated on the device (row_ptr monotone and
  *             row_ptr[n] == 2m, ids < n, rows strictly ascending, no loops,

@@ -555,6 +555,50 @@ size_t engine_header_bytes(uint32_t S) {
          up(sizeof(Ctl));
 }
 
+// Pinned host buffers and events of the plain entry point, kept per host
+// thread and reused by its later calls (calls on one thread never overlap).
+// They live until the process ends: freeing them from a thread-exit
+// destructor could run after the HIP runtime has shut down.
+struct HostCache {
+  void* pinned = nullptr;
+  size_t bytes = 0;
+  int dev = -1;
+  hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};  // two polling, two timing
+  hoStatus ensure(size_t need) {
+    int d = 0;
+    HIPCHK(hipGetDevice(&d));
+    if (d != dev) {  // events belong to the device current at creation
+      for (auto& e : ev) {
+        if (e) (void)hipEventDestroy(e);
+        e = nullptr;
+      }
+      HIPCHK(hipEventCreateWithFlags(&ev[0], hipEventDisableTiming));
+      HIPCHK(hipEventCreateWithFlags(&ev[1], hipEventDisableTiming));
+      HIPCHK(hipEventCreate(&ev[2]));
+      HIPCHK(hipEventCreate(&ev[3]));
+      dev = d;
+    }
+    if (need > bytes) {
+      if (pinned) (void)hipHostFree(pinned);
+      pinned = nullptr;
+      bytes = 0;
+      HIPCHK(hipHostMalloc(&pinned, need, hipHostMallocDefault));
+      bytes = need;
+    }
+    return HO_OK;
+  }
+};
+
+HostCache& host_cache() {
+  static thread_local HostCache* c = new HostCache();
+  return *c;
+}
+
+// Pinned bytes an engine of S slots polls and stages through.
+size_t host_bytes(uint32_t S) {
+  return up(8ull * HO_STATUS_WORDS * S + sizeof(Ctl)) + 2 * sizeof(Dev) * (size_t)S;
+}
+
 class Engine {
  public:
   hipStream_t s = nullptr;
@@ -581,6 +625,7 @@ class Engine {
   Dev* idle_h = nullptr;      // pinned: descriptor of each idle slot
   Dev* dev_h = nullptr;       // pinned: staging of each admitted slot's descriptor
   hipEvent_t ev[2] = {nullptr, nullptr};
+  bool borrowed_host = false;  // pinned buffers and events belong to the thread's cache
   hipGraphExec_t exec[3] = {nullptr, nullptr, nullptr};
   bool owns_graphs = false;
   bool copy_failed = false;
@@ -591,6 +636,7 @@ class Engine {
     if (owns_graphs)
       for (auto& e : exec)
         if (e) (void)hipGraphExecDestroy(e);
+    if (borrowed_host) return;
     for (auto& e : ev)
       if (e) (void)hipEventDestroy(e);
     if (hstat) (void)hipHostFree(hstat);
@@ -599,7 +645,7 @@ class Engine {
   }
 
   hoStatus init(void* ws, size_t ws_bytes, uint32_t slots, uint32_t hmax_, const RoundGrid& grid,
-                hipStream_t stream, bool plain_) {
+                hipStream_t stream, bool plain_, bool borrow_host = false) {
     s = stream;
     base = ((uintptr_t)ws + ALIGN - 1) / ALIGN * ALIGN;
     if (ws_bytes < ALIGN + engine_header_bytes(slots)) return HO_ERR_WORKSPACE;
@@ -620,12 +666,23 @@ class Engine {
     live_seen.assign(S, 0);
     compact_at.assign(S, 0);
     compact_each.assign(S, 0);
-    HIPCHK(hipHostMalloc((void**)&hstat, 8ull * HO_STATUS_WORDS * S + sizeof(Ctl),
-                         hipHostMallocDefault));
-    HIPCHK(hipHostMalloc((void**)&idle_h, sizeof(Dev) * S, hipHostMallocDefault));
-    HIPCHK(hipHostMalloc((void**)&dev_h, sizeof(Dev) * S, hipHostMallocDefault));
-    HIPCHK(hipEventCreateWithFlags(&ev[0], hipEventDisableTiming));
-    HIPCHK(hipEventCreateWithFlags(&ev[1], hipEventDisableTiming));
+    if (borrow_host) {
+      HostCache& hc = host_cache();
+      HOCHK(hc.ensure(host_bytes(S)));
+      hstat = (uint32_t*)hc.pinned;
+      idle_h = (Dev*)((char*)hc.pinned + up(8ull * HO_STATUS_WORDS * S + sizeof(Ctl)));
+      dev_h = idle_h + S;
+      ev[0] = hc.ev[0];
+      ev[1] = hc.ev[1];
+      borrowed_host = true;
+    } else {
+      HIPCHK(hipHostMalloc((void**)&hstat, 8ull * HO_STATUS_WORDS * S + sizeof(Ctl),
+                           hipHostMallocDefault));
+      HIPCHK(hipHostMalloc((void**)&idle_h, sizeof(Dev) * S, hipHostMallocDefault));
+      HIPCHK(hipHostMalloc((void**)&dev_h, sizeof(Dev) * S, hipHostMallocDefault));
+      HIPCHK(hipEventCreateWithFlags(&ev[0], hipEventDisableTiming));
+      HIPCHK(hipEventCreateWithFlags(&ev[1], hipEventDisableTiming));
+    }
     // every slot starts idle: finished status, a descriptor with no levels
     // whose control block says finished, so every round kernel returns at once
     for (uint32_t i = 0; i < HO_STATUS_WORDS * S; ++i) hstat[i] = (i % HO_STATUS_WORDS == 0) ? 1u : 0u;
@@ -916,21 +973,48 @@ hoStatus run_rounds_host(const Dev& d, const RoundGrid& g, hipStream_t s, bool t
   hoStatus st = read_ctl(d, &c, s);
   uint64_t rounds = 0;
   uint32_t compact_at = compact_next(d.m);
+  // Stats mode, environment HOTRUSS_ROUND_LOG = path: one line per round
+  // (level, jump, peel-set size, work items, events, work counters, kernel
+  // times) for studying how the work is spread over rounds.
+  FILE* rlog = nullptr;
+  if (timed) {
+    if (const char* path = std::getenv("HOTRUSS_ROUND_LOG")) {
+      rlog = std::fopen(path, "w");
+      if (rlog)
+        std::fprintf(rlog, "r k jump nR items2 live ev_top lv_items lv_slots lv_cand lv_probes "
+                           "lv_drops su_items su_slots su_hits us_jump us_mark us_level us_support "
+                           "us_advance\n");
+    }
+  }
   while (st == HO_OK && !c.done) {
     if (c.live <= compact_at || (d.serial & HO_FLAG_COMPACT_EACH)) {
       launch_compact(d, s);
       compact_at = compact_next(c.live);
     }
+    double kms0[KT_N];
+    for (int i = 0; i < KT_N; ++i) kms0[i] = timed ? kms[i] : 0.0;
+    const Ctl before = c;
     if ((st = tm.begin(s)) != HO_OK) break;
     hipLaunchKernelGGL(k_jump_min, dim3(g.jump), dim3(T), 0, s, dp);
     if ((st = tm.end(s, KT_JUMP)) != HO_OK) break;
     if ((st = tm.begin(s)) != HO_OK) break;
     hipLaunchKernelGGL(k_mark, dim3(g.mark), dim3(T), 0, s, dp);
     if ((st = tm.end(s, KT_MARK)) != HO_OK) break;
+    Ctl mid;
+    if (rlog && (st = read_ctl(d, &mid, s)) != HO_OK) break;
     st = steps_host(d, g, s, 2, false, tm);
     if (st == HO_OK) st = read_ctl(d, &c, s);
+    if (rlog && st == HO_OK) {
+      std::fprintf(rlog, "%u %u %u %u %u %u %llu", mid.r, mid.k, mid.jump, mid.nR, mid.nit[2],
+                   c.live, (unsigned long long)(c.events - before.events));
+      for (uint32_t i = 0; i < NSTAT; ++i)
+        std::fprintf(rlog, " %llu", (unsigned long long)(c.stat[i] - before.stat[i]));
+      for (int i = KT_JUMP; i <= KT_ADVANCE; ++i) std::fprintf(rlog, " %.1f", (kms[i] - kms0[i]) * 1e3);
+      std::fputc('\n', rlog);
+    }
     if (++rounds > (uint64_t)d.m + 2) st = HO_ERR_INTERNAL;
   }
+  if (rlog) std::fclose(rlog);
   return st;
 }
 
@@ -1054,7 +1138,7 @@ hoStatus hoTrussDecompose(const uint32_t* row_ptr, const uint32_t* col_idx, uint
   const bool host_loop = stats || (tune && (tune->flags & HO_FLAG_HOST_LOOP));
   const RoundGrid g = plain_grid(m, tune);
   Engine eng;
-  HOCHK(eng.init(workspace, workspace_bytes, 1, p.h, g, stream, true));
+  HOCHK(eng.init(workspace, workspace_bytes, 1, p.h, g, stream, true, true));
   Request r;
   r.rp = row_ptr; r.ci = col_idx; r.n = n; r.m = m; r.h = h;
   r.t = out_trussness; r.rho = out_round;
@@ -1064,9 +1148,8 @@ hoStatus hoTrussDecompose(const uint32_t* row_ptr, const uint32_t* col_idx, uint
   if (st == HO_ERR_BUDGET) return HO_ERR_WORKSPACE;
   HOCHK(st);
   hoStats out{};
-  EventGuard ev0, ev1, es0, es1;  // destroyed on every return path
-  HIPCHK(hipEventCreate(&ev0.e));
-  HIPCHK(hipEventCreate(&ev1.e));
+  EventGuard es0, es1;  // destroyed on every return path
+  struct { hipEvent_t e; } ev0{host_cache().ev[2]}, ev1{host_cache().ev[3]};
   if (stats) {
     HIPCHK(hipEventCreate(&es0.e));
     HIPCHK(hipEventCreate(&es1.e));

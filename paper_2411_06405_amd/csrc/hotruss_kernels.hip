@@ -296,54 +296,88 @@ struct RoundCtx {
 __device__ __forceinline__ RoundCtx round_ctx(const Ctl* c) { return RoundCtx{c->r, c->k, c->r & 1}; }
 
 // ---- work item emission (all 64 lanes call; per-lane counts may be 0) ----
-// Items over a CSR row: nv = deg + extra virtual entries, CHUNK per item;
-// virtual index 0 is the extra candidate when extra = 1.  Writes `nch` items
-// starting at list index idx (reserved by the caller).
-__device__ __forceinline__ void put_row_items(const Dev& d, uint32_t list, uint32_t idx,
-                                              uint32_t nch, uint32_t kind, uint32_t x, uint32_t y,
-                                              uint32_t base, uint32_t nv, uint32_t extra) {
+// A lane's group of items covers one CSR row (or one ball row's words), CHUNK
+// entries per item.  The wave reserves the items of all its lanes with one
+// atomic and writes them cooperatively, consecutive lanes on consecutive list
+// entries, so a lane whose row belongs to a hub (hundreds of items) does not
+// write them alone.
+//   ITEM_ROW    Item{x, y, base, meta(kind, extra, len, vstart)}: nv virtual
+//               entries (the row's slots, plus the extra candidate at virtual
+//               index 0 when extra = 1)
+//   ITEM_SLOTS  Item{x, y, base + vstart, meta(0, 0, len, 0)}: support items
+//   ITEM_WORDS  Item{x, y, vstart, meta(KIND_A_WORDS, 0, len, 0)}: ball words
+enum { ITEM_ROW = 0, ITEM_SLOTS = 1, ITEM_WORDS = 2 };
+
+__device__ __forceinline__ uint32_t chunks_of(uint32_t nv) { return (nv + CHUNK - 1) / CHUNK; }
+
+// Lane 0 reserves `total` entries of a counter for the whole wave.
+__device__ __forceinline__ uint32_t reserve_wave(uint32_t* counter, uint32_t total) {
+  uint32_t b = 0;
+  if (lane_id() == 0 && total) b = atomicAdd(counter, total);
+  return __shfl(b, 0, WAVE);
+}
+
+// Write the wave's groups: this lane's items are entries [first + excl,
+// first + excl + cnt) of list `list` (excl: exclusive prefix of cnt over the
+// wave, total: the wave's sum; both from wave_excl_scan).
+template <int MODE>
+__device__ void emit_items_wave(const Dev& d, uint32_t list, uint32_t first, uint32_t total,
+                                uint32_t excl, uint32_t cnt, uint32_t kind, uint32_t extra,
+                                uint32_t x, uint32_t y, uint32_t base, uint32_t nv) {
+  const uint32_t incl = excl + cnt;
   bool over = false;
-  for (uint32_t c = 0; c < nch; ++c) {
-    const uint32_t vs = c * CHUNK;
-    if (idx + c < d.itcap)
-      d.itl[list][idx + c] = Item{x, y, base, item_meta(kind, extra, min(CHUNK, nv - vs), vs)};
-    else over = true;
+  for (uint32_t t0 = 0; t0 < total; t0 += WAVE) {
+    const uint32_t t = t0 + lane_id();
+    // owner of entry t: the number of lanes whose groups end at or before t
+    uint32_t own = 0;
+#pragma unroll
+    for (uint32_t step = 32; step > 0; step >>= 1) {
+      const uint32_t v = (uint32_t)__shfl(incl, (int)(own + step - 1), WAVE);
+      if (v <= t) own += step;
+    }
+    const uint32_t ox = __shfl(x, own, WAVE), oy = __shfl(y, own, WAVE);
+    const uint32_t ob = __shfl(base, own, WAVE), onv = __shfl(nv, own, WAVE);
+    const uint32_t oex = __shfl(excl, own, WAVE);
+    if (t < total) {
+      const uint32_t vs = (t - oex) * CHUNK;
+      const uint32_t len = min(CHUNK, onv - vs);
+      Item it;
+      if (MODE == ITEM_ROW) it = Item{ox, oy, ob, item_meta(kind, extra, len, vs)};
+      else if (MODE == ITEM_SLOTS) it = Item{ox, oy, ob + vs, item_meta(0, 0, len, 0)};
+      else it = Item{ox, oy, vs, item_meta(KIND_A_WORDS, 0, len, 0)};
+      const uint32_t idx = first + t;
+      if (idx < d.itcap) d.itl[list][idx] = it;
+      else over = true;
+    }
   }
   if (over) d.ctl->iovf[list] = 1;
+}
+
+// One group per lane with its own reservation.
+template <int MODE>
+__device__ void emit_group(const Dev& d, uint32_t list, uint32_t kind, uint32_t extra, uint32_t x,
+                           uint32_t y, uint32_t base, uint32_t nv) {
+  const uint32_t cnt = chunks_of(nv);
+  uint32_t total;
+  const uint32_t excl = wave_excl_scan(cnt, &total);
+  if (!total) return;
+  const uint32_t first = reserve_wave(&d.ctl->nit[list], total);
+  emit_items_wave<MODE>(d, list, first, total, excl, cnt, kind, extra, x, y, base, nv);
 }
 
 // Support items of event (a -> w): the live edges (a,b), CHUNK slots per item.
 __device__ void emit_support_items(const Dev& d, bool active, uint32_t a, uint32_t w) {
-  const uint32_t list = d.h + 1;
-  uint32_t nch = 0, base = 0, deg = 0;
+  uint32_t base = 0, deg = 0;
   if (active) {
     base = d.rp[a];
     deg = row_end(d, a) - base;
-    nch = (deg + CHUNK - 1) / CHUNK;
   }
-  const uint32_t slot = wave_reserve(&d.ctl->nit[list], nch);
-  Item* L = d.itl[list];
-  bool over = false;
-  for (uint32_t c = 0; c < nch; ++c) {
-    const uint32_t idx = slot + c;
-    if (idx < d.itcap) L[idx] = Item{a, w, base + c * CHUNK, item_meta(0, 0, min(CHUNK, deg - c * CHUNK), 0)};
-    else over = true;
-  }
-  if (over) d.ctl->iovf[list] = 1;
+  emit_group<ITEM_SLOTS>(d, d.h + 1, 0, 0, a, w, base, deg);
 }
 
 // Items over z's old (j-1)-ball words for candidates (x, w), j >= 3.
 __device__ void emit_word_items(const Dev& d, uint32_t j, bool active, uint32_t x, uint32_t z) {
-  const uint32_t nch = active ? (d.W + CHUNK - 1) / CHUNK : 0;
-  const uint32_t slot = wave_reserve(&d.ctl->nit[j], nch);
-  bool over = false;
-  for (uint32_t c = 0; c < nch; ++c) {
-    const uint32_t idx = slot + c;
-    if (idx < d.itcap)
-      d.itl[j][idx] = Item{x, z, c * CHUNK, item_meta(KIND_A_WORDS, 0, min(CHUNK, d.W - c * CHUNK), 0)};
-    else over = true;
-  }
-  if (over) d.ctl->iovf[j] = 1;
+  emit_group<ITEM_WORDS>(d, j, 0, 0, x, z, 0, active ? d.W : 0u);
 }
 
 // Record `cnt` (0..2) events of this lane at level j (all lanes call).
@@ -423,15 +457,20 @@ __device__ void mark_edge(const Dev& d, const RoundCtx& rc, bool valid, uint32_t
     bb = d.rp[b];
     db = row_end(d, b) - bb;
   }
-  const uint32_t n0 = valid ? (db + CHUNK) / CHUNK : 0;      // (a, y), y in N(b); + (a, b)
-  const uint32_t n1 = valid ? (da + CHUNK) / CHUNK : 0;      // (b, y), y in N(a); + (b, a)
-  const uint32_t n2 = valid ? (da + CHUNK - 1) / CHUNK : 0;  // (y, b), y in N(a)
-  const uint32_t n3 = valid ? (db + CHUNK - 1) / CHUNK : 0;  // (y, a), y in N(b)
-  const uint32_t slot = wave_reserve(&d.ctl->nit[2], n0 + n1 + n2 + n3);
-  put_row_items(d, 2, slot, n0, KIND_A_SLOTS, a, b, bb, db + 1, 1);
-  put_row_items(d, 2, slot + n0, n1, KIND_A_SLOTS, b, a, ba, da + 1, 1);
-  put_row_items(d, 2, slot + n0 + n1, n2, KIND_B_SLOTS, a, b, ba, da, 0);
-  put_row_items(d, 2, slot + n0 + n1 + n2, n3, KIND_B_SLOTS, b, a, bb, db, 0);
+  // virtual entries per group: (a, y), y in N(b), plus (a, b); (b, y), y in
+  // N(a), plus (b, a); (y, b), y in N(a); (y, a), y in N(b)
+  const uint32_t v0 = valid ? db + 1 : 0, v1 = valid ? da + 1 : 0, v2 = valid ? da : 0,
+                 v3 = valid ? db : 0;
+  const uint32_t n0 = chunks_of(v0), n1 = chunks_of(v1), n2 = chunks_of(v2), n3 = chunks_of(v3);
+  uint32_t t0, t1, t2, t3;
+  const uint32_t e0 = wave_excl_scan(n0, &t0), e1 = wave_excl_scan(n1, &t1);
+  const uint32_t e2 = wave_excl_scan(n2, &t2), e3 = wave_excl_scan(n3, &t3);
+  const uint32_t first = reserve_wave(&d.ctl->nit[2], t0 + t1 + t2 + t3);
+  emit_items_wave<ITEM_ROW>(d, 2, first, t0, e0, n0, KIND_A_SLOTS, 1, a, b, bb, v0);
+  emit_items_wave<ITEM_ROW>(d, 2, first + t0, t1, e1, n1, KIND_A_SLOTS, 1, b, a, ba, v1);
+  emit_items_wave<ITEM_ROW>(d, 2, first + t0 + t1, t2, e2, n2, KIND_B_SLOTS, 0, a, b, ba, v2);
+  emit_items_wave<ITEM_ROW>(d, 2, first + t0 + t1 + t2, t3, e3, n3, KIND_B_SLOTS, 0, b, a, bb,
+                            v3);
   for (uint32_t j = 3; j <= d.h; ++j) {
     emit_word_items(d, j, valid, a, b);
     emit_word_items(d, j, valid, b, a);
@@ -553,11 +592,14 @@ __global__ void __launch_bounds__(LV_THREADS) k_level(const Dev* __restrict__ de
   const RoundCtx rc = round_ctx(c);
   const uint32_t nit = min(c->nit[j], d.itcap);
   const uint32_t wave = threadIdx.x / WAVE, lane = lane_id();
+  // items are dealt to workgroups first, then to their waves, so a round
+  // with few items still spreads its candidates (and their probes) over as
+  // many CUs as it has items
   const uint32_t stride = gridDim.x * LV_WAVES;
-  uint32_t it = blockIdx.x * LV_WAVES + wave;
+  uint32_t it = wave * gridDim.x + blockIdx.x;
   const bool counting = d.spart != nullptr;
   if (counting && threadIdx.x < 5) s_stat[threadIdx.x] = 0;
-  if (blockIdx.x * LV_WAVES >= nit) {  // whole workgroup idle
+  if (blockIdx.x >= nit) {  // whole workgroup idle
     if (counting && threadIdx.x < 5) d.spart[threadIdx.x * STAT_GRID + blockIdx.x] = 0;
     return;
   }
@@ -712,7 +754,6 @@ __global__ void __launch_bounds__(LV_THREADS) k_level(const Dev* __restrict__ de
       {
         const uint32_t extra = j == d.h ? 0u : 1u;
         const uint32_t list = j == d.h ? d.h + 1 : j + 1;
-        const uint32_t kind = j == d.h ? 0u : KIND_B_SLOTS;
         uint32_t bx = 0, nx = 0, bw = 0, nw = 0;
         if (w1) {
           bx = d.rp[x];
@@ -722,23 +763,18 @@ __global__ void __launch_bounds__(LV_THREADS) k_level(const Dev* __restrict__ de
           bw = d.rp[w];
           nw = row_end(d, w) - bw + extra;
         }
-        const uint32_t c1 = (nx + CHUNK - 1) / CHUNK, c2 = (nw + CHUNK - 1) / CHUNK;
-        const uint32_t slot = wave_reserve(&d.ctl->nit[list], c1 + c2);
+        const uint32_t c1 = chunks_of(nx), c2 = chunks_of(nw);
+        uint32_t t1, t2;
+        const uint32_t e1 = wave_excl_scan(c1, &t1), e2 = wave_excl_scan(c2, &t2);
+        const uint32_t first = reserve_wave(&d.ctl->nit[list], t1 + t2);
         if (j == d.h) {
           // support items carry the slot base of their chunk
-          for (uint32_t c = 0; c < c1; ++c) {
-            if (slot + c < d.itcap)
-              d.itl[list][slot + c] = Item{x, w, bx + c * CHUNK, item_meta(0, 0, min(CHUNK, nx - c * CHUNK), 0)};
-            else d.ctl->iovf[list] = 1;
-          }
-          for (uint32_t c = 0; c < c2; ++c) {
-            if (slot + c1 + c < d.itcap)
-              d.itl[list][slot + c1 + c] = Item{w, x, bw + c * CHUNK, item_meta(0, 0, min(CHUNK, nw - c * CHUNK), 0)};
-            else d.ctl->iovf[list] = 1;
-          }
+          emit_items_wave<ITEM_SLOTS>(d, list, first, t1, e1, c1, 0, 0, x, w, bx, nx);
+          emit_items_wave<ITEM_SLOTS>(d, list, first + t1, t2, e2, c2, 0, 0, w, x, bw, nw);
         } else {
-          put_row_items(d, list, slot, c1, kind, x, w, bx, nx, extra);
-          put_row_items(d, list, slot + c1, c2, kind, w, x, bw, nw, extra);
+          emit_items_wave<ITEM_ROW>(d, list, first, t1, e1, c1, KIND_B_SLOTS, 1, x, w, bx, nx);
+          emit_items_wave<ITEM_ROW>(d, list, first + t1, t2, e2, c2, KIND_B_SLOTS, 1, w, x, bw,
+                                    nw);
         }
       }
     }
@@ -785,23 +821,47 @@ __global__ void __launch_bounds__(256) k_support(const Dev* __restrict__ devs) {
   const uint64_t* Lh = d.L[d.h];
   const uint64_t* Dh = d.Dm[d.h];
   uint32_t* Rn = d.R[rc.p ^ 1];
-  for (uint32_t it = blockIdx.x * wpb + threadIdx.x / WAVE; it < nit; it += gridDim.x * wpb) {
-    const Item I = d.itl[list][it];
-    const uint32_t len = meta_len(I.meta);
-    bool push = false, hit = false;
-    uint32_t e = 0;
-    if (lane < len) {
+  const Item* items = d.itl[list];
+  const uint32_t stride = gridDim.x * wpb;
+  // items dealt to workgroups first, then to their waves; software-pipelined:
+  // the next item and its slots (state, neighbour, edge id) load while the
+  // current item's ball words and support atomics are in flight
+  uint32_t it = (threadIdx.x / WAVE) * gridDim.x + blockIdx.x;
+  Item I{0, 0, 0, 0};
+  uint32_t sr = 0, b = 0, e = 0;
+  if (it < nit) {
+    I = items[it];
+    if (lane < meta_len(I.meta)) {
       const uint32_t q = I.base + lane;
-      if (d.srem[q] > rc.r) {
-        const uint32_t b = d.cix[q];
-        e = d.eid[q];
-        const size_t o = (size_t)I.y * d.W + (b >> 6);
-        uint64_t word = Lh[o];
-        if (I.x < b) word |= Dh[o];
-        hit = (word >> (b & 63)) & 1ull;
-        if (hit) push = atomicSub(&d.sup[e], 1u) == rc.k - 1;
+      sr = d.srem[q];
+      b = d.cix[q];
+      e = d.eid[q];
+    }
+  }
+  while (it < nit) {
+    const uint32_t len = meta_len(I.meta);
+    const bool live = lane < len && sr > rc.r;
+    uint64_t word = 0;
+    if (live) {
+      const size_t o = (size_t)I.y * d.W + (b >> 6);
+      word = Lh[o];
+      if (I.x < b) word |= Dh[o];
+    }
+    const uint32_t nx = it + stride;
+    Item I2{0, 0, 0, 0};
+    uint32_t sr2 = 0, b2 = 0, e2 = 0;
+    if (nx < nit) {
+      I2 = items[nx];
+      if (lane < meta_len(I2.meta)) {
+        const uint32_t q = I2.base + lane;
+        sr2 = d.srem[q];
+        b2 = d.cix[q];
+        e2 = d.eid[q];
       }
     }
+    const bool hit = live && ((word >> (b & 63)) & 1ull);
+    bool push = false;
+    if (hit) push = atomicSub(&d.sup[e], 1u) == rc.k - 1;
     const uint32_t slot = wave_reserve(&c->nPush, push ? 1u : 0u);
     if (push) Rn[slot] = e;
     if (counting) {
@@ -812,6 +872,11 @@ __global__ void __launch_bounds__(256) k_support(const Dev* __restrict__ devs) {
         atomicAdd(&s_stat[2], hits);
       }
     }
+    I = I2;
+    sr = sr2;
+    b = b2;
+    e = e2;
+    it = nx;
   }
   if (counting) {
     __syncthreads();
@@ -900,17 +965,8 @@ __device__ __forceinline__ void fill_event_items(const Dev& d, uint32_t list, bo
     bx = d.rp[x];
     nx = d.len[x] + (support ? 0u : 1u);
   }
-  const uint32_t nch = (nx + CHUNK - 1) / CHUNK;
-  const uint32_t slot = wave_reserve(&d.ctl->nit[list], nch);
-  if (support) {
-    for (uint32_t q = 0; q < nch; ++q) {
-      if (slot + q < d.itcap)
-        d.itl[list][slot + q] = Item{x, w, bx + q * CHUNK, item_meta(0, 0, min(CHUNK, nx - q * CHUNK), 0)};
-      else d.ctl->iovf[list] = 1;
-    }
-  } else {
-    put_row_items(d, list, slot, nch, KIND_B_SLOTS, x, w, bx, nx, 1);
-  }
+  if (support) emit_group<ITEM_SLOTS>(d, list, 0, 0, x, w, bx, nx);
+  else emit_group<ITEM_ROW>(d, list, KIND_B_SLOTS, 1, x, w, bx, nx);
 }
 
 // Change-mark bits [blo, bhi) of level jm as events (x -> w): follow-up
@@ -997,10 +1053,13 @@ __global__ void __launch_bounds__(256) k_fill_level(const Dev* __restrict__ dp, 
         bx = d.rp[x];
         dx = d.len[x];
       }
-      const uint32_t n0 = a ? (dz + CHUNK) / CHUNK : 0, n1 = a ? (dx + CHUNK - 1) / CHUNK : 0;
-      const uint32_t slot = wave_reserve(&d.ctl->nit[2], n0 + n1);
-      put_row_items(d, 2, slot, n0, KIND_A_SLOTS, x, z, bz, dz + 1, 1);
-      put_row_items(d, 2, slot + n0, n1, KIND_B_SLOTS, x, z, bx, dx, 0);
+      const uint32_t v0 = a ? dz + 1 : 0, v1 = a ? dx : 0;
+      const uint32_t n0 = chunks_of(v0), n1 = chunks_of(v1);
+      uint32_t t0, t1;
+      const uint32_t e0 = wave_excl_scan(n0, &t0), e1 = wave_excl_scan(n1, &t1);
+      const uint32_t first = reserve_wave(&d.ctl->nit[2], t0 + t1);
+      emit_items_wave<ITEM_ROW>(d, 2, first, t0, e0, n0, KIND_A_SLOTS, 1, x, z, bz, v0);
+      emit_items_wave<ITEM_ROW>(d, 2, first + t0, t1, e1, n1, KIND_B_SLOTS, 0, x, z, bx, v1);
     } else {
       emit_word_items(d, j, a, x, z);  // (x, w), w in z's old (j-1)-ball
     }

@@ -174,3 +174,20 @@ def test_hindex_binding_rejects_unknown_pruning_on_the_host(ht):
         ht.hindex(rp, ci, 2, 2, pruning="bogus")
     with pytest.raises(ValueError):
         ht.hindex_workspace(rp, ci, 2, 2, pruning="bogus")
+
+
+def test_vertex_cap_of_the_ball_rows(ht):
+    # a ball row (ceil(n/64) words, rounded up to 8) must fit the 64 KiB of
+    # LDS a workgroup builds it in: n <= 524,288; above that every entry point
+    # that keeps balls refuses before any device work
+    lib = ht.lib
+    cap = 524_288
+    assert ht.workspace_bytes(cap, 1000, 2) > 0
+    assert ht.workspace_bytes(cap + 1, 1000, 2) == 0
+    assert lib.hoTrussHIndexWorkspaceBytes(cap, 1000, 2) > 0
+    assert lib.hoTrussHIndexWorkspaceBytes(cap + 1, 1000, 2) == 0
+    fake = C.c_void_p(0x1000)
+    big = C.c_size_t(1 << 62)
+    assert lib.hoTrussDecompose(fake, fake, cap + 1, 5, 2, fake, None, fake, big, None,
+                                None) == -1
+    assert lib.hoTrussHSupport(fake, fake, cap + 1, 5, 2, fake, fake, big, None, None) == -1

@@ -37,19 +37,57 @@ def _decompose_like_bench(g, h):
     return out
 
 
-@pytest.mark.parametrize("make,h,nsample", [
-    (lambda: W.d2(), 2, 3000),          # Chung-Lu n = 100,000 (the bench workload)
-    (lambda: W.d3(), 2, 400),           # R-MAT scale 18
-])
-def test_fullsize_certified(make, h, nsample):
-    g = make()
-    t, rho, sup, st = _decompose_like_bench(g, h)
+def _check_any_size(t, rho, sup, st):
     # properties at any size: 2 <= t <= sup_G + 2; rounds numbered 0..R-1
     assert t.min() >= 2 and np.all(t <= sup.astype(np.int64) + 2)
     assert int(rho.max()) + 1 == st["rounds"]
     assert np.unique(rho).size == st["rounds"]
+
+
+@pytest.mark.parametrize("make,h,nsample", [
+    (lambda: W.d2(), 2, 3000),          # Chung-Lu n = 100,000
+    (lambda: W.d3(), 2, 2000),          # R-MAT scale 18, h = 2 (the bench workload)
+    (lambda: W.d3(), 3, 2000),          # R-MAT scale 18, h = 3
+], ids=["chung_lu_100k_h2", "rmat18_h2", "rmat18_h3"])
+def test_fullsize_certified(make, h, nsample):
+    # C0 on every edge; C1 and C2 on nsample uniform edges plus the edges of
+    # the first and last round and of the lowest and highest trussness
+    g = make()
+    t, rho, sup, st = _decompose_like_bench(g, h)
+    _check_any_size(t, rho, sup, st)
     n = assert_certified(g, h, t, rho, nsample)
     print(f"[gpu] certified {n} sampled edges, {st['rounds']} rounds", flush=True)
+
+
+@pytest.mark.parametrize("scale", [12, 13, 14])
+def test_rmat_h3_fully_certified(scale):
+    # R-MAT of the bench's parameters at scales the certificate covers edge by
+    # edge: C0, C1 and C2 on every edge, so t is exact everywhere (Def. 4)
+    import os
+    import oracle
+    g = W.d3(scale=scale)
+    t, rho, sup, st = _decompose_like_bench(g, 3)
+    _check_any_size(t, rho, sup, st)
+    ok, fail = oracle.certify(g, 3, t, rho, sample=None,
+                              threads=len(os.sched_getaffinity(0)))
+    assert ok, f"R-MAT {scale} h=3: certificate check {fail}"
+    print(f"[gpu] certified all {g.m} edges, {st['rounds']} rounds", flush=True)
+
+
+# Serving size classes (Chung-Lu, n in {50k, 200k}), each the first request of
+# its class and h in the seeded request stream
+D5_CLASS_REQUESTS = {"n50k_h3": 27, "n50k_h4": 5, "n200k_h2": 4, "n200k_h3": 24}
+
+
+@pytest.mark.parametrize("which", sorted(D5_CLASS_REQUESTS))
+def test_serving_classes_certified(which):
+    spec = W.d5_request_specs(200)[D5_CLASS_REQUESTS[which]]
+    g = W.d5_graph(spec)
+    h = spec[3]
+    t, rho, sup, st = _decompose_like_bench(g, h)
+    _check_any_size(t, rho, sup, st)
+    n = assert_certified(g, h, t, rho, 2000)
+    print(f"[gpu] {which}: certified {n} sampled edges, {st['rounds']} rounds", flush=True)
 
 
 def test_fullsize_initial_support_sampled():
