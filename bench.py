@@ -94,6 +94,36 @@ def recorded_traffic(kernel: str, workload: str):
     return None
 
 
+def recorded_whole_traffic(workload: str):
+    """HBM bytes of one whole decomposition (every library kernel, scaled
+    counters) from the committed summary, if taken on the current kernels."""
+    tfile = PROFILES / f"traffic_whole_{workload}.txt"
+    if tfile.exists():
+        t = json.loads(tfile.read_text())
+        if t.get("source_sha") == kernel_source_sha("k_level"):
+            return t.get("bytes_per_decomposition")
+    return None
+
+
+def whole_run(st: dict, workload: str, device_ms: float):
+    """The whole decomposition against the HBM roofline and the method-level
+    count: (i) counter bytes / device time / 8 TB/s, (ii) counter bytes /
+    B_alg (below 1: the incremental kernels move less than re-evaluating the
+    affected edges would), (iii) evaluations per second."""
+    measured = recorded_whole_traffic(workload)
+    alg = st.get("alg_bytes") or None
+    evals = st.get("evaluations") or None
+    out = {"evaluations": evals, "alg_bytes_method": alg, "counter_bytes": measured,
+           "device_ms_median": device_ms}
+    if measured and device_ms:
+        out["counter_frac"] = measured / (device_ms * 1e-3) / (HBM_PEAK_GBS * 1e9)
+    if measured and alg:
+        out["traffic_efficiency"] = measured / alg
+    if evals and device_ms:
+        out["evaluations_per_s"] = evals / (device_ms * 1e-3)
+    return out
+
+
 def roofline_from_stats(st: dict, workload: str):
     """Roofline object of the dominant round kernel from a stats-mode run."""
     km, kl, work = st["kernel_ms"], st["kernel_launches"], st["work"]
@@ -557,6 +587,8 @@ def main(argv=None):
     ap.add_argument("--loads", type=float, nargs="+", default=[0.5, 0.8],
                     help="serve: arrival rates as fractions of the measured capacity")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-stats", action="store_true",
+                    help="skip the stats-mode decomposition (profiling runs)")
     ap.add_argument("--hx-h", type=int, default=2, help="hindex: hop threshold h")
     ap.add_argument("--hx-sync-only", action="store_true",
                     help="hindex: time the synchronous sweeps only (profiling runs)")
@@ -609,9 +641,15 @@ def main(argv=None):
     _log(f"timed: {ms:.1f} ms per decomposition")
     # one more decomposition with every round kernel timed by HIP events on
     # this stream and the chunked kernels' work counted (host-driven rounds)
-    ht.decompose(rp, ci, g.n, h, workspace=ws, device=dev, tune=stats_tune)
-    torch.cuda.synchronize()
-    stt = ht.last_stats()
+    stt = None
+    if not args.no_stats:
+        _log("stats-mode decomposition (host-driven rounds, per-kernel HIP events)")
+        ts, _ = ht.decompose(rp, ci, g.n, h, workspace=ws, device=dev, tune=stats_tune)
+        torch.cuda.synchronize()
+        stt = ht.last_stats()
+        if args.steps > 0:
+            assert torch.equal(ts, t), "stats-mode decomposition differs"
+    dmed = float(np.median(device_ms)) if device_ms else None
 
     line = {
         "metric": "edges/s to h-trussness (h=2)" if h == 2 else f"edges/s to h-trussness (h={h})",
@@ -628,8 +666,10 @@ def main(argv=None):
                       "runs": len(device_ms)},
         "edges_per_s_device_median": (g.m / (float(np.median(device_ms)) * 1e-3)
                                       if device_ms else None),
-        "roofline": roofline_from_stats(stt, args.workload),
-        "kernel_ms_stats_mode": {k: round(v, 3) for k, v in stt["kernel_ms"].items()},
+        "roofline": roofline_from_stats(stt, args.workload) if stt else None,
+        "kernel_ms_stats_mode": ({k: round(v, 3) for k, v in stt["kernel_ms"].items()}
+                                 if stt else None),
+        "whole_run": whole_run(stt or {}, args.workload, dmed),
     }
     if args.calibrate:
         _calibration_copy(torch, dev)

@@ -122,8 +122,27 @@ typedef struct {
     /* HO_FLAG_STATS only: work done by the chunked kernels.  Ball-change
      * events: [0] work items, [1] candidate slots examined, [2] candidate pairs
      * tested, [3] witness probes, [4] pairs dropped (directed events).  Support
-     * update: [5] work items, [6] adjacency slots, [7] common h-neighbours lost. */
+     * update: [5] work items, [6] adjacency slots, [7] common h-neighbours lost.
+     * Witness tests done on bitset rows count one probe per word pair. */
     uint64_t work[8];
+    /* HO_FLAG_STATS only (0 otherwise, and 0 if an event list overflowed):
+     * the method-level work of the same round schedule done the re-evaluating
+     * way (Section 3): evaluations = m + the live edges, summed over rounds,
+     * that have an endpoint whose h-ball changed in the round; alg_bytes = per
+     * evaluation (u,v) s(u) + s(v) + 4 with s(x) = min(4|N(x,h)|, ceil(n/8)),
+     * plus per ball build min(frontier reads of a bounded BFS to depth h-1 at
+     * 8 + 4 deg per vertex reached, h full scans 4(n+1) + 8|S| + ceil(n/8)),
+     * builds being every non-isolated vertex at the start and, in each round,
+     * the vertices within h-1 hops (before the round) of a removed edge's
+     * endpoint.  A round that removes every remaining edge counts nothing. */
+    uint64_t evaluations;
+    uint64_t alg_bytes;
+    /* Ball-change events per level j = 1..h (index j-1): pairs {x, w}, counted
+     * once per direction, that left the j-hop ball in some round; level 1
+     * counts both directions of every removed edge.  The round that removes
+     * every remaining edge updates no ball above level 1, so for j >= 2 this
+     * is sum_x |N_G(x,j)| - sum_x |N_S(x,j)|, S the edges of that last round. */
+    uint64_t level_events[16];
 } hoStats;
 
 /* Bytes of device workspace hoTrussDecompose / hoTrussHSupport need for a

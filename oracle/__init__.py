@@ -10,8 +10,9 @@ from .oracle import (OracleError, build, certify, decompose, h_support, h_suppor
 from .brute import brute_trussness, brute_h_support
 from .components import truss_components
 from .hindex import hindex_sequence, hindex_trussness
+from . import accounting
 
 __all__ = ["OracleError", "build", "certify", "decompose", "h_support", "h_support_edges",
            "lib_path",
            "brute_trussness", "brute_h_support", "truss_components",
-           "hindex_sequence", "hindex_trussness"]
+           "hindex_sequence", "hindex_trussness", "accounting"]

@@ -45,7 +45,8 @@ class Stats(C.Structure):
                 ("overflows", C.c_uint64), ("compactions", C.c_uint64),
                 ("device_ms", C.c_double),
                 ("kernel_ms", C.c_double * 6), ("kernel_launches", C.c_uint64 * 6),
-                ("work", C.c_uint64 * 8)]
+                ("work", C.c_uint64 * 8), ("evaluations", C.c_uint64),
+                ("alg_bytes", C.c_uint64), ("level_events", C.c_uint64 * 16)]
 
 
 KERNEL_KINDS = ("support_init", "jump_min", "mark", "level_events", "support_update", "advance")
@@ -191,7 +192,9 @@ def last_stats() -> dict:
             "overflows": s.overflows, "compactions": s.compactions, "device_ms": s.device_ms,
             "kernel_ms": dict(zip(KERNEL_KINDS, list(s.kernel_ms))),
             "kernel_launches": dict(zip(KERNEL_KINDS, list(s.kernel_launches))),
-            "work": dict(zip(WORK_KINDS, list(s.work)))}
+            "work": dict(zip(WORK_KINDS, list(s.work))),
+            "evaluations": s.evaluations, "alg_bytes": s.alg_bytes,
+            "level_events": list(s.level_events)}
 
 
 def to_numpy_u32(t: torch.Tensor) -> np.ndarray:

@@ -35,7 +35,7 @@ struct Plan {
   size_t off_ctl, off_eid, off_eu, off_ev, off_s1, off_s2, off_srem, off_upcnt, off_upoff,
       off_scan, off_minpart, off_sup, off_rho, off_R0, off_R1, off_L[HMAX + 1],
       off_Dm[HMAX + 1], off_evl[HMAX + 1][2], off_itl[HMAX + 2], off_cix, off_len, off_tci,
-      off_teid;
+      off_teid, off_acct;
   size_t total = 0;
 };
 
@@ -89,6 +89,7 @@ bool make_plan(uint32_t n, uint64_t m, uint32_t h, const hoTuning* tune, bool fu
   p.off_teid = take(full ? 8 * m + 4 : 0);
   p.off_R0 = take(full ? 4 * m + 4 : 0);
   p.off_R1 = take(full ? 4 * m + 4 : 0);
+  p.off_acct = take(full ? 6 * (4 * (size_t)n + 4) : 0);  // stats-mode work count
   for (uint32_t j = 0; j <= HMAX; ++j) {
     p.off_L[j] = p.off_Dm[j] = 0;
     p.off_evl[j][0] = p.off_evl[j][1] = 0;
@@ -132,6 +133,7 @@ bool make_topo_plan(uint32_t n, uint64_t m, Plan* P, size_t* off_cc) {
   p.off_minpart = take(4 * MIN_PART);
   p.off_sup = take(4 * m + 4);
   p.off_rho = p.off_R0 = p.off_R1 = p.off_cix = p.off_len = p.off_tci = p.off_teid = 0;
+  p.off_acct = 0;
   for (uint32_t j = 0; j <= HMAX; ++j) {
     p.off_L[j] = p.off_Dm[j] = 0;
     p.off_evl[j][0] = p.off_evl[j][1] = 0;
@@ -202,6 +204,14 @@ Dev carve(const Plan& p, void* ws, const uint32_t* rp, const uint32_t* ci, uint3
     d.len = (uint32_t*)at(p.off_len);
     d.tci = (uint32_t*)at(p.off_tci);
     d.teid = (uint32_t*)at(p.off_teid);
+    uint32_t* acct = (uint32_t*)at(p.off_acct);
+    const size_t na = (size_t)p.n + 1;
+    d.acct_ball = acct;
+    d.acct_deg = acct + na;
+    d.acct_stamp = acct + 2 * na;
+    d.acct_vstamp = acct + 3 * na;
+    d.acct_list = acct + 4 * na;
+    d.acct_vlist = acct + 5 * na;
   }
   for (uint32_t j = 1; j <= p.h; ++j) {
     d.L[j] = (uint64_t*)at(p.off_L[j]);
@@ -452,6 +462,14 @@ hoStatus steps_host(const Dev& d, const RoundGrid& g, hipStream_t s, uint32_t fr
       recover = c.halt != 0;
     }
     if (recover) HOCHK(recover_step(d, g, s, step, tm));
+  }
+  if (d.spart) {
+    // stats mode: the method-level work count of this round (not timed)
+    const unsigned ag = (unsigned)num_cu() * 4;
+    hipLaunchKernelGGL(k_acct_round1, dim3(ag), dim3(T), 0, s, dp);
+    hipLaunchKernelGGL(k_acct_round2, dim3(ag), dim3(T), 0, s, dp);
+    hipLaunchKernelGGL(k_acct_round3, dim3(ag), dim3(T), 0, s, dp);
+    hipLaunchKernelGGL(k_acct_reset, dim3(1), dim3(64), 0, s, dp);
   }
   HOCHK(tm.begin(s));
   hipLaunchKernelGGL(k_advance, dim3(1), dim3(64), 0, s, dp);
@@ -1169,6 +1187,11 @@ hoStatus hoTrussDecompose(const uint32_t* row_ptr, const uint32_t* col_idx, uint
       d.spart = eng.spart_d;
       HIPCHK(hipMemsetAsync(d.spart, 0, 4ull * NSTAT * STAT_GRID, stream));
       HIPCHK(hipMemcpyAsync(d.self, &d, sizeof(Dev), hipMemcpyHostToDevice, stream));
+      // method-level work count: ball sizes and degrees in G, the initial pass
+      const unsigned ag = (unsigned)num_cu() * 4;
+      hipLaunchKernelGGL(k_acct_init, dim3(grid_for(d.n, 4)), dim3(256), 0, stream, d.self);
+      hipLaunchKernelGGL(k_acct_start, dim3(ag), dim3(256), 0, stream, d.self);
+      HIPCHK(hipGetLastError());
     }
     HOCHK(run_rounds_host(d, g, stream, stats, out.kernel_ms, out.kernel_launches));
   } else {
@@ -1191,6 +1214,11 @@ hoStatus hoTrussDecompose(const uint32_t* row_ptr, const uint32_t* col_idx, uint
   out.compactions = c.compactions;
   out.device_ms = ms;
   for (uint32_t i = 0; i < NSTAT; ++i) out.work[i] = c.stat[i];
+  if (stats && !c.acct_incomplete) {
+    out.evaluations = c.acct_evals;
+    out.alg_bytes = c.acct_bytes;
+  }
+  for (uint32_t j = 1; j <= std::min<uint32_t>(p.h, 16); ++j) out.level_events[j - 1] = c.levents[j];
   t_stats = out;
   return HO_OK;
 }

@@ -64,7 +64,15 @@ struct Ctl {
   uint32_t iovf[HMAX + 2];    // work item list overflowed
   uint32_t compactions;  // adjacency compactions done (statistics)
   uint32_t recovering;   // the host is re-running an overflowed step in windows
-  uint32_t pad[5];
+  // stats mode: method-level work count (support evaluations and bytes of the
+  // re-evaluating peeling method on the same round schedule)
+  uint32_t acct_nch;     // vertices whose h-ball changed this round (listed)
+  uint32_t acct_nv;      // ball builds of this round (listed)
+  uint32_t acct_incomplete;  // an event list overflowed: the count is a lower bound
+  uint32_t pad[2];
+  uint64_t acct_evals;
+  uint64_t acct_bytes;
+  uint64_t levents[HMAX + 1];  // ball-change events per level, all rounds
   // stats mode: work counters, level kernel [0..5), support kernel [5..8)
   uint64_t stat[NSTAT];
 };
@@ -110,6 +118,14 @@ struct Dev {
   uint32_t* spart;         // stats mode: per-workgroup counters [NSTAT][STAT_GRID], else null
   uint32_t* status;        // this slot's {done, halt, live, -} words in the engine's status
                            // array (done: 1 finished, 2 malformed CSR; live: edges left)
+  // stats mode, method-level work count: per vertex |N(x,h)|, live degree,
+  // round stamps (h-ball changed, ball build counted) and this round's lists
+  uint32_t* acct_ball;
+  uint32_t* acct_deg;
+  uint32_t* acct_stamp;
+  uint32_t* acct_vstamp;
+  uint32_t* acct_list;
+  uint32_t* acct_vlist;
 };
 
 __device__ __forceinline__ uint32_t lane_id() { return threadIdx.x & (WAVE - 1); }

@@ -402,9 +402,25 @@ __global__ void __launch_bounds__(256) k_jump_min(const Dev* __restrict__ devs) 
   const uint32_t p = c->r & 1, q = p ^ 1;
   if (blockIdx.x == 0 && threadIdx.x == 0) d.ctl->jump = (c->nR == 0);
   if (c->nR == 0) {
+    // four edges per thread in flight: both loads unconditional
     uint32_t mn = 0xffffffffu;
-    for (uint32_t e = blockIdx.x * blockDim.x + threadIdx.x; e < d.m; e += gridDim.x * blockDim.x)
-      if (d.t[e] == 0) mn = min(mn, d.sup[e]);
+    const uint32_t stride = gridDim.x * blockDim.x;
+    uint32_t e = blockIdx.x * blockDim.x + threadIdx.x;
+    for (; e + 3 * stride < d.m; e += 4 * stride) {
+      uint32_t tv[4], sv[4];
+#pragma unroll
+      for (uint32_t u = 0; u < 4; ++u) {
+        tv[u] = d.t[e + u * stride];
+        sv[u] = d.sup[e + u * stride];
+      }
+#pragma unroll
+      for (uint32_t u = 0; u < 4; ++u)
+        if (tv[u] == 0) mn = min(mn, sv[u]);
+    }
+    for (; e < d.m; e += stride) {
+      const uint32_t tv = d.t[e], sv = d.sup[e];
+      if (tv == 0) mn = min(mn, sv);
+    }
     mn = wave_min(mn);
     if (lane_id() == 0) smin[threadIdx.x / WAVE] = mn;
     __syncthreads();
@@ -499,7 +515,9 @@ __global__ void __launch_bounds__(256) k_mark(const Dev* __restrict__ devs) {
     }
     for (uint32_t base = wbase; base < d.m; base += wstride) {
       const uint32_t e = base + lane;
-      const bool take = e < d.m && d.t[e] == 0 && d.sup[e] + 2 <= rc.k;
+      const uint32_t tv = e < d.m ? d.t[e] : 1u, sv = e < d.m ? d.sup[e] : 0xffffffffu;
+      const bool take = tv == 0 && sv <= rc.k - 2;
+      if (!__ballot(take)) continue;  // nothing to peel in these 64 edges
       const uint32_t i = wave_reserve(&c->nR, take ? 1u : 0u);
       if (take) d.R[rc.p][i] = e;
       mark_edge(d, rc, take, e, i);
@@ -572,7 +590,8 @@ __global__ void __launch_bounds__(LV_THREADS) k_level(const Dev* __restrict__ de
   __shared__ uint32_t cx[LV_CAP], cw[LV_CAP], cb[LV_CAP], cbeg[LV_CAP], cdeg[LV_CAP],
       coff[LV_CAP];
   __shared__ uint32_t cflag[LV_CAP];
-  __shared__ uint32_t s_count, s_busy[2], s_wsum[LV_WAVES];
+  __shared__ uint32_t cdense[LV_CAP];  // candidates tested by bitset rows (see the flush)
+  __shared__ uint32_t s_count, s_busy[2], s_wsum[LV_WAVES], s_ndense;
   __shared__ uint32_t s_stat[5];  // stats mode: items, slots, candidates, probes, drops
   Ctl* c = d.ctl;
   if (c->done) return;
@@ -716,8 +735,32 @@ __global__ void __launch_bounds__(LV_THREADS) k_level(const Dev* __restrict__ de
     par ^= 1;
     if (n == 0 && !busy) break;
     if (n + LV_THREADS <= LV_CAP && busy) continue;
-    // ---- flush: probe every buffered pair ----
+    // ---- flush: look for a witness of every buffered pair ----
+    // A pair whose lower-degree endpoint has more active slots than a ball
+    // row has words is tested on the bitset rows instead: the witnesses are
+    // exactly the members of L[1](low) & L[j-1](other) (L[1] holds the live
+    // closed neighbourhood, and low itself is not within j-1 hops of the
+    // other endpoint), so one wave ANDs the two rows and stops at the first
+    // non-zero word.  The other pairs' probes (a live neighbour y of the
+    // lower-degree endpoint, checked against the other's (j-1)-ball) are laid
+    // out flat over all threads of the workgroup.
+    if (threadIdx.x == 0) s_ndense = 0;
+    __syncthreads();
+    for (uint32_t base = 0; base < n; base += LV_THREADS) {
+      const uint32_t i = base + threadIdx.x;
+      const bool dense = i < n && cdeg[i] > d.W;
+      const uint64_t bd = __ballot(dense);  // one LDS reservation per wave
+      uint32_t at = 0;
+      if (lane == 0 && bd) at = atomicAdd(&s_ndense, (uint32_t)__popcll(bd));
+      at = __shfl(at, 0, WAVE) + (uint32_t)__popcll(bd & ((1ull << lane) - 1));
+      if (dense) {
+        cdense[at] = i;
+        cdeg[i] = 0;
+      }
+    }
+    __syncthreads();
     const uint32_t total = block_scan_cap(cdeg, coff, n, s_wsum);
+    const uint32_t ndense = s_ndense;
     if (counting && threadIdx.x == 0) s_stat[3] += total;
     for (uint32_t pidx = threadIdx.x; pidx < total; pidx += LV_THREADS) {
       uint32_t lo = 0, hi = n;
@@ -728,6 +771,28 @@ __global__ void __launch_bounds__(LV_THREADS) k_level(const Dev* __restrict__ de
       if (cflag[lo]) continue;
       const uint32_t q = cbeg[lo] + (pidx - coff[lo]);
       if (d.srem[q] > rc.r && getbit(Lp, d.W, cb[lo], d.cix[q])) cflag[lo] = 1;
+    }
+    for (uint32_t k = wave; k < ndense; k += LV_WAVES) {
+      const uint32_t i = cdense[k];
+      const uint32_t hi = cb[i], lo = (hi == cx[i]) ? cw[i] : cx[i];
+      const uint64_t* ra = row(d.L[1], d.W, lo);
+      const uint64_t* rb = row(Lp, d.W, hi);
+      uint32_t words = 0;
+      bool found = false;
+      for (uint32_t w0 = 0; w0 < d.W && !found; w0 += 4 * WAVE) {
+        uint64_t any = 0;
+#pragma unroll
+        for (uint32_t u = 0; u < 4; ++u) {
+          const uint32_t wi = w0 + u * WAVE + lane;
+          if (wi < d.W) any |= ra[wi] & rb[wi];
+        }
+        words += min(4 * WAVE, d.W - w0);
+        found = __ballot(any != 0) != 0;
+      }
+      if (lane == 0) {
+        if (found) cflag[i] = 1;
+        if (counting) atomicAdd(&s_stat[3], words);  // a word pair counts as one probe
+      }
     }
     __syncthreads();
     // ---- pairs without a witness leave the j-ball (both directions) ----
@@ -913,6 +978,7 @@ __global__ void k_advance(const Dev* __restrict__ devs) {
   const uint32_t p = c->r & 1, q = p ^ 1;
   c->nev[1][p] = 2 * c->nR;  // level-1 events: both directions of every peeled edge
   c->events += c->nev[d.h][p];
+  for (uint32_t j = 1; j <= d.h; ++j) c->levents[j] += c->nev[j][p];
   c->jump = 0;
   uint32_t any = 0;
   for (uint32_t j = 1; j <= d.h; ++j) {
@@ -1150,6 +1216,219 @@ __global__ void k_init_rows(Dev d) {
     d.cix[i] = d.ci[i];
   for (uint32_t x = blockIdx.x * blockDim.x + threadIdx.x; x < d.n; x += gridDim.x * blockDim.x)
     d.len[x] = d.rp[x + 1] - d.rp[x];
+}
+
+// ============================================ method-level work count
+// Stats mode only.  On the bulk round schedule the kernels follow, count what
+// the re-evaluating form of the peeling method (Section 3) would do:
+//   evaluations  every edge once at the start, then in each round the live
+//                edges with an endpoint whose h-ball changed (an endpoint with
+//                a top-level ball-change event: h-support depends only on the
+//                two endpoint balls, Def. 3);
+//   bytes        per evaluation (u,v): s(u) + s(v) + 4, s(x) = min(4 |N(x,h)|,
+//                ceil(n/8)) (the smaller exact encoding of a ball); per ball
+//                build: min(frontier reads of a bounded BFS to depth h-1,
+//                8 + 4 deg per vertex reached; h full scans of the CSR and a
+//                bitset); builds: every non-isolated vertex at the start, then
+//                in each round the vertices within h-1 hops (before the round)
+//                of an endpoint of a removed edge.  A round that removes every
+//                remaining edge evaluates and builds nothing.
+// Per-vertex ball sizes and live degrees are kept from the round's top-level
+// events and removals.
+
+__device__ __forceinline__ uint64_t wave_sum64(uint64_t v) {
+  for (int o = WAVE / 2; o > 0; o >>= 1) v += __shfl_xor(v, o, WAVE);
+  return v;
+}
+
+__device__ __forceinline__ uint64_t acct_s(const Dev& d, uint32_t x) {
+  return min((uint64_t)4 * d.acct_ball[x], (uint64_t)((d.n + 7) / 8));
+}
+
+// Cost of building x's ball in the live edge set after round r (all lanes
+// call with the same x; every lane gets the wave total).  live_m: |S|.
+__device__ uint64_t acct_build(const Dev& d, uint32_t x, uint32_t r, uint64_t live_m) {
+  uint64_t f = 0;
+  const uint32_t lane = lane_id();
+  if (lane == 0) f = 8 + 4ull * d.acct_deg[x];
+  if (d.h == 2) {
+    for (uint32_t q = d.rp[x] + lane; q < row_end(d, x); q += WAVE)
+      if (d.srem[q] > r) f += 8 + 4ull * d.acct_deg[d.cix[q]];
+  } else if (d.h >= 3) {
+    const uint64_t* B = row(d.L[d.h - 1], d.W, x);
+    for (uint32_t i = lane; i < d.W; i += WAVE) {
+      uint64_t wd = B[i];
+      if (i == (x >> 6)) wd &= ~(1ull << (x & 63));  // x itself is counted above
+      while (wd) {
+        const uint32_t y = i * 64 + (uint32_t)(__ffsll((unsigned long long)wd) - 1);
+        wd &= wd - 1;
+        f += 8 + 4ull * d.acct_deg[y];
+      }
+    }
+  }
+  f = wave_sum64(f);
+  const uint64_t scans = (uint64_t)d.h * (4ull * (d.n + 1) + 8 * live_m + (d.n + 7) / 8);
+  return min(f, scans);
+}
+
+// Start: ball sizes and degrees in G (one wave per vertex), stamps cleared.
+__global__ void __launch_bounds__(256) k_acct_init(const Dev* __restrict__ dp) {
+  const Dev& d = *dp;
+  if (d.ctl->err) return;
+  const uint32_t lane = lane_id(), wpb = blockDim.x / WAVE;
+  for (uint32_t x = blockIdx.x * wpb + threadIdx.x / WAVE; x < d.n; x += gridDim.x * wpb) {
+    const uint64_t* B = row(d.L[d.h], d.W, x);
+    uint32_t c = 0;
+    for (uint32_t i = lane; i < d.W; i += WAVE) c += (uint32_t)__popcll(B[i]);
+    c = wave_sum(c);
+    if (lane == 0) {
+      d.acct_ball[x] = c - 1;
+      d.acct_deg[x] = d.rp[x + 1] - d.rp[x];
+      d.acct_stamp[x] = 0;
+      d.acct_vstamp[x] = 0;
+    }
+  }
+}
+
+// Start: the initial pass (every edge evaluated, every non-isolated vertex's
+// ball built in G).
+__global__ void __launch_bounds__(256) k_acct_start(const Dev* __restrict__ dp) {
+  const Dev& d = *dp;
+  if (d.ctl->err) return;
+  uint64_t bytes = 0;
+  for (uint32_t e = blockIdx.x * blockDim.x + threadIdx.x; e < d.m; e += gridDim.x * blockDim.x)
+    bytes += acct_s(d, d.eu[e]) + acct_s(d, d.ev[e]) + 4;
+  bytes = wave_sum64(bytes);
+  const uint32_t wpb = blockDim.x / WAVE;
+  uint64_t builds = 0;
+  for (uint32_t x = blockIdx.x * wpb + threadIdx.x / WAVE; x < d.n; x += gridDim.x * wpb)
+    if (d.acct_deg[x]) builds += acct_build(d, x, 0, d.m);
+  if (lane_id() == 0) {
+    atomicAdd((unsigned long long*)&d.ctl->acct_bytes, (unsigned long long)(bytes + builds));
+    if (blockIdx.x == 0 && threadIdx.x == 0)
+      atomicAdd((unsigned long long*)&d.ctl->acct_evals, (unsigned long long)d.m);
+  }
+}
+
+// True when this round leaves edges for the count (not finished, not the
+// round that removes everything).
+__device__ __forceinline__ bool acct_round_counts(const Ctl* c) {
+  return !c->done && !c->halt && !c->err && c->nR < c->live;
+}
+
+// Round, step 1: degrees after the removals; vertices whose h-ball changed
+// (sources of top-level events; at h = 1 the events are the removals), their
+// ball sizes after the round, listed once each.
+__global__ void __launch_bounds__(256) k_acct_round1(const Dev* __restrict__ dp) {
+  const Dev& d = *dp;
+  Ctl* c = d.ctl;
+  if (!acct_round_counts(c)) return;
+  const RoundCtx rc = round_ctx(c);
+  const uint32_t stride = gridDim.x * blockDim.x, tid = blockIdx.x * blockDim.x + threadIdx.x;
+  const uint32_t nR = c->nR;
+  for (uint32_t i = tid; i < 2 * nR; i += stride) {
+    const uint32_t e = d.R[rc.p][i >> 1];
+    atomicSub(&d.acct_deg[(i & 1) ? d.ev[e] : d.eu[e]], 1u);
+  }
+  const bool from_removals = d.h == 1;
+  if (!from_removals && c->ovf[d.h][rc.p]) {
+    if (tid == 0) c->acct_incomplete = 1;
+    return;
+  }
+  const uint32_t ne = from_removals ? 2 * nR : min(c->nev[d.h][rc.p], d.evcap);
+  for (uint32_t i = tid; i < ne; i += stride) {
+    uint32_t x;
+    if (from_removals) {
+      const uint32_t e = d.R[rc.p][i >> 1];
+      x = (i & 1) ? d.ev[e] : d.eu[e];
+    } else {
+      x = (uint32_t)(d.evl[d.h][rc.p][i] >> 32);
+    }
+    atomicSub(&d.acct_ball[x], 1u);
+    if (atomicExch(&d.acct_stamp[x], rc.r + 1) != rc.r + 1)
+      d.acct_list[atomicAdd(&c->acct_nch, 1u)] = x;
+  }
+}
+
+// Round, step 2: the evaluations (each live edge at a changed vertex once: by
+// its smaller endpoint when both changed) and the ball builds, listed once
+// each: the vertices within h-1 hops, before the round, of a removed edge's
+// endpoint (at h-1 = 1 the endpoint and its neighbours then; above, the old
+// (h-1)-ball = L[h-1] plus the pairs that left it this round).
+__global__ void __launch_bounds__(256) k_acct_round2(const Dev* __restrict__ dp) {
+  const Dev& d = *dp;
+  Ctl* c = d.ctl;
+  if (!acct_round_counts(c) || c->acct_incomplete) return;
+  const RoundCtx rc = round_ctx(c);
+  const uint32_t lane = lane_id(), wpb = blockDim.x / WAVE;
+  const uint32_t wid = blockIdx.x * wpb + threadIdx.x / WAVE, nw = gridDim.x * wpb;
+  uint64_t evals = 0, bytes = 0;
+  const uint32_t nch = c->acct_nch;
+  for (uint32_t k = wid; k < nch; k += nw) {
+    const uint32_t x = d.acct_list[k];
+    const uint64_t sx = acct_s(d, x);
+    for (uint32_t q = d.rp[x] + lane; q < row_end(d, x); q += WAVE) {
+      if (d.srem[q] <= rc.r) continue;
+      const uint32_t b = d.cix[q];
+      if (d.acct_stamp[b] == rc.r + 1 && b < x) continue;  // counted from b
+      evals += 1;
+      bytes += sx + acct_s(d, b) + 4;
+    }
+  }
+  const uint32_t nR = c->nR;
+  for (uint32_t k = wid; k < 2 * nR; k += nw) {
+    const uint32_t e = d.R[rc.p][k >> 1];
+    const uint32_t z = (k & 1) ? d.ev[e] : d.eu[e];
+    auto claim = [&](uint32_t x) {
+      if (atomicExch(&d.acct_vstamp[x], rc.r + 1) != rc.r + 1)
+        d.acct_vlist[atomicAdd(&c->acct_nv, 1u)] = x;
+    };
+    if (lane == 0) claim(z);
+    if (d.h == 2) {
+      for (uint32_t q = d.rp[z] + lane; q < row_end(d, z); q += WAVE)
+        if (d.srem[q] >= rc.r) claim(d.cix[q]);
+    } else if (d.h >= 3) {
+      const uint64_t* B = row(d.L[d.h - 1], d.W, z);
+      const uint64_t* D = row(d.Dm[d.h - 1], d.W, z);
+      for (uint32_t i = lane; i < d.W; i += WAVE) {
+        uint64_t wd = B[i] | D[i];
+        while (wd) {
+          claim(i * 64 + (uint32_t)(__ffsll((unsigned long long)wd) - 1));
+          wd &= wd - 1;
+        }
+      }
+    }
+  }
+  evals = wave_sum64(evals);
+  bytes = wave_sum64(bytes);
+  if (lane == 0) {
+    if (evals) atomicAdd((unsigned long long*)&c->acct_evals, (unsigned long long)evals);
+    if (bytes) atomicAdd((unsigned long long*)&c->acct_bytes, (unsigned long long)bytes);
+  }
+}
+
+// Round, step 3: the listed ball builds, in the edge set after the round;
+// the round's lists are emptied for the next round.
+__global__ void __launch_bounds__(256) k_acct_round3(const Dev* __restrict__ dp) {
+  const Dev& d = *dp;
+  Ctl* c = d.ctl;
+  if (!acct_round_counts(c) || c->acct_incomplete) return;
+  const RoundCtx rc = round_ctx(c);
+  const uint32_t wpb = blockDim.x / WAVE;
+  const uint64_t live_m = c->live - c->nR;
+  uint64_t bytes = 0;
+  const uint32_t nv = c->acct_nv;
+  for (uint32_t k = blockIdx.x * wpb + threadIdx.x / WAVE; k < nv; k += gridDim.x * wpb)
+    bytes += acct_build(d, d.acct_vlist[k], rc.r, live_m);
+  if (lane_id() == 0 && bytes)
+    atomicAdd((unsigned long long*)&c->acct_bytes, (unsigned long long)bytes);
+}
+
+// After step 3 (one thread): the round's lists are empty again.
+__global__ void k_acct_reset(const Dev* __restrict__ dp) {
+  if (blockIdx.x != 0 || threadIdx.x != 0) return;
+  dp->ctl->acct_nch = 0;
+  dp->ctl->acct_nv = 0;
 }
 
 // ============================================ (k,h)-truss extraction

@@ -6,7 +6,9 @@ Writes OUTDIR/kernels_TAG.txt (per-kernel dispatch count and durations from
 --kernel-trace), OUTDIR/hbm_counters_TAG.txt (mean FETCH_SIZE / WRITE_SIZE per
 dispatch, KiB) and OUTDIR/traffic_KERNEL_TAG.txt for the kernels named in
 KERNEL_SOURCES (HBM bytes per launch, scaled by what the same counters read
-for a 256 MiB device-to-device copy).
+for a 256 MiB device-to-device copy), and OUTDIR/traffic_whole_TAG.txt: the
+scaled bytes of every library kernel (names starting with k_) per
+decomposition, a decomposition being one dispatch of k_init_ctl.
 """
 from __future__ import annotations
 
@@ -85,6 +87,16 @@ def main(trace_db, fetch_db, write_db, outdir, tag, cmd):
         lines.append(f"{short(n):40s} {len(f):8d} {f.mean() if len(f) else 0:14.2f} "
                      f"{w.mean() if len(w) else 0:14.2f}")
     (outdir / f"hbm_counters_{tag}.txt").write_text("\n".join(lines) + "\n")
+    if sf is not None and sw is not None:
+        lib = [n for n in set(fetch) | set(write) if short(n).startswith("k_")]
+        tot = sum(float(fetch.get(n, np.zeros(0)).sum()) * 1024 * sf +
+                  float(write.get(n, np.zeros(0)).sum()) * 1024 * sw for n in lib)
+        ndec = sum(len(fetch[n]) for n in fetch if short(n) == "k_init_ctl")
+        if ndec:
+            (outdir / f"traffic_whole_{tag}.txt").write_text(json.dumps({
+                "source_sha": source_sha("hotruss_kernels.hip"), "decompositions": ndec,
+                "bytes_per_decomposition": tot / ndec, "fetch_scale": sf, "write_scale": sw,
+                "command": cmd}, indent=1) + "\n")
     for kname, srcname in KERNEL_SOURCES.items():
         sha = source_sha(srcname)
         full = [n for n in fetch if short(n) == kname]
