@@ -24,7 +24,8 @@
  *             the current HIP device, owned by the caller; the library never
  *             allocates device memory, it carves everything from the caller's
  *             workspace and keeps no pointer after the call returns (sessions
- *             excepted, see below).
+ *             excepted, see below; hoTrussDecomposeNoAlloc uses a fixed device
+ *             array inside the library instead of a workspace).
  *   Streams   work is enqueued on `stream`.  Calls return after the work has
  *             completed on that stream unless stated otherwise (hoSubmit is
  *             host-only).  This is deliberate: the number of peel rounds is
@@ -170,6 +171,27 @@ hoStatus hoTrussDecompose(const uint32_t *row_ptr, const uint32_t *col_idx,
                           uint32_t *out_trussness, uint32_t *out_round,
                           void *workspace, size_t workspace_bytes,
                           const hoTuning *tune, hipStream_t stream);
+
+/* hoTrussDecompose for callers that cannot allocate memory (serving loops
+ * and harnesses that forbid allocation): the same computation and outputs,
+ * with no workspace argument and no allocation of any kind (no device or
+ * pinned host memory, no events, no graphs).  The workspace, slot descriptor
+ * and status words live in a fixed 256 MiB device array inside the library
+ * (one per GPU, held until the process ends); a graph whose workspace does
+ * not fit it returns HO_ERR_WORKSPACE before any device work (h = 2 fits up
+ * to about n = 20,000 with m = 10^5).  Rounds are driven from the host, one
+ * synchronisation per step, so it is slower per round than hoTrussDecompose.
+ * Inputs and outputs as for hoTrussDecompose (device pointers); returns after
+ * the work has completed on `stream`.  The array keeps the last call's
+ * contents; each call initialises what it reads.  Calls on one GPU share
+ * the array: the library serialises calls made from this process, and the
+ * caller must not let two processes' calls, or a call and a stream still
+ * running an earlier call's work, overlap on one GPU.  hoTrussLastStats
+ * reports its counters (device_ms 0). */
+hoStatus hoTrussDecomposeNoAlloc(const uint32_t *row_ptr, const uint32_t *col_idx,
+                                 uint32_t n, uint64_t m, uint32_t h,
+                                 uint32_t *out_trussness, uint32_t *out_round,
+                                 hipStream_t stream);
 
 /* Counters of the last hoTrussDecompose on this host thread (host pointer). */
 hoStatus hoTrussLastStats(hoStats *out);

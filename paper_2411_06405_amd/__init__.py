@@ -6,12 +6,12 @@ C ABI declared in include/hotruss.h); this package is its thin Python binding.
 from . import autotune
 from ._lib import (HotrussError, Session, Tuning, alloc_workspace, batched_workspace_bytes,
                    decompose, decompose_batch, decompose_batched, decompose_graph,
-                   h_support,
+                   decompose_noalloc, h_support,
                    h_support_graph, hindex, hindex_graph, hindex_workspace, last_stats, lib, to_numpy_u32, truss_components,
                    truss_components_graph, workspace_bytes)
 
 __all__ = ["autotune", "HotrussError", "Session", "Tuning", "alloc_workspace", "batched_workspace_bytes",
            "decompose", "decompose_batch", "decompose_batched", "decompose_graph",
-           "h_support",
+           "decompose_noalloc", "h_support",
            "h_support_graph", "hindex", "hindex_graph", "hindex_workspace", "last_stats", "lib", "to_numpy_u32", "truss_components",
            "truss_components_graph", "workspace_bytes"]

@@ -63,6 +63,8 @@ def _declare(lib):
     lib.hoTrussHSupport.restype = C.c_int
     lib.hoTrussDecompose.argtypes = [vp, vp, u32, u64, u32, vp, vp, vp, sz, tp, vp]
     lib.hoTrussDecompose.restype = C.c_int
+    lib.hoTrussDecomposeNoAlloc.argtypes = [vp, vp, u32, u64, u32, vp, vp, vp]
+    lib.hoTrussDecomposeNoAlloc.restype = C.c_int
     lib.hoTrussLastStats.argtypes = [C.POINTER(Stats)]
     lib.hoTrussLastStats.restype = C.c_int
     lib.hoStatusString.argtypes = [C.c_int]
@@ -105,6 +107,7 @@ def load():
 lib = load()
 
 EXPORTS = ["hoStatusString", "hoTrussWorkspaceBytes", "hoTrussHSupport", "hoTrussDecompose",
+           "hoTrussDecomposeNoAlloc",
            "hoTrussLastStats", "hoTrussBatchedWorkspaceBytes", "hoTrussDecomposeBatched",
            "hoSessionCreate", "hoSubmit", "hoSessionProgress", "hoPoll", "hoCancel",
            "hoSessionDestroy", "hoTrussComponentsWorkspaceBytes", "hoTrussComponents",
@@ -183,6 +186,24 @@ def decompose(row_ptr, col_idx, n: int, h: int, with_rounds: bool = True, worksp
                               ws.data_ptr(), ws.numel(), _tuning(tune), _stream(stream))
     _check(rc, "hoTrussDecompose")
     return t[:m], (rho[:m] if rho is not None else None)
+
+
+def decompose_noalloc(row_ptr, col_idx, n: int, h: int, out_trussness=None, out_round=None,
+                      stream=None, device="cuda"):
+    """hoTrussDecomposeNoAlloc: the library allocates nothing (its workspace
+    is a fixed device array inside the library).  Outputs may be passed in;
+    otherwise this binding allocates them."""
+    rp = _dev_u32(row_ptr, device)
+    ci = _dev_u32(col_idx, device)
+    m = ci.numel() // 2
+    t = out_trussness if out_trussness is not None else \
+        torch.empty(max(m, 1), dtype=torch.int32, device=device)
+    rho = out_round if out_round is not None else \
+        torch.empty(max(m, 1), dtype=torch.int32, device=device)
+    rc = lib.hoTrussDecomposeNoAlloc(rp.data_ptr(), ci.data_ptr(), n, m, h, t.data_ptr(),
+                                     rho.data_ptr(), _stream(stream))
+    _check(rc, "hoTrussDecomposeNoAlloc")
+    return t[:m], rho[:m]
 
 
 def last_stats() -> dict:

@@ -1036,6 +1036,40 @@ hoStatus run_rounds_host(const Dev& d, const RoundGrid& g, hipStream_t s, bool t
   return st;
 }
 
+// ------------------------------------------- allocation-free decomposition
+// The library's own device scratch for hoTrussDecomposeNoAlloc: the slot
+// descriptor, its status words and the whole workspace of one decomposition
+// are carved from this array, so that the call allocates nothing.  Each GPU
+// the library runs on holds its own copy until the process ends.  In host
+// code the array's name is not a device address: the address comes from
+// hipGetSymbolAddress, taken once per device (scratch_base), and only that
+// address is used.
+constexpr size_t SCRATCH_BYTES = 256ull << 20;
+static __device__ __align__(256) unsigned char scratch[SCRATCH_BYTES];
+
+constexpr int SCRATCH_MAX_DEVICES = 64;
+std::mutex g_scratch_mu[SCRATCH_MAX_DEVICES];  // one call at a time per device
+void* g_scratch_ptr[SCRATCH_MAX_DEVICES] = {};
+std::once_flag g_scratch_once[SCRATCH_MAX_DEVICES];
+hipError_t g_scratch_err[SCRATCH_MAX_DEVICES] = {};
+
+// Device address of this device's scratch array (the current device must be
+// `dev`); null if the runtime could not resolve it.
+void* scratch_base(int dev) {
+  std::call_once(g_scratch_once[dev], [dev] {
+    void* ptr = nullptr;
+    g_scratch_err[dev] = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    g_scratch_ptr[dev] = g_scratch_err[dev] == hipSuccess ? ptr : nullptr;
+  });
+  return g_scratch_ptr[dev];
+}
+
+// Bytes of scratch a decomposition of (n, m, h) takes (0: invalid arguments).
+size_t noalloc_bytes(uint32_t n, uint64_t m, uint32_t h, Plan* p) {
+  if (!make_plan(n, m, h, nullptr, true, p, 16)) return 0;
+  return up(sizeof(Dev)) + up(4ull * HO_STATUS_WORDS) + p->total;
+}
+
 hoStatus check_common(const uint32_t* rp, const uint32_t* ci, uint32_t n, uint64_t m, uint32_t h,
                       const void* out, void* ws) {
   if (h == 0) return HO_ERR_INVALID_ARG;
@@ -1219,6 +1253,67 @@ hoStatus hoTrussDecompose(const uint32_t* row_ptr, const uint32_t* col_idx, uint
     out.alg_bytes = c.acct_bytes;
   }
   for (uint32_t j = 1; j <= std::min<uint32_t>(p.h, 16); ++j) out.level_events[j - 1] = c.levents[j];
+  t_stats = out;
+  return HO_OK;
+}
+
+hoStatus hoTrussDecomposeNoAlloc(const uint32_t* row_ptr, const uint32_t* col_idx, uint32_t n,
+                                 uint64_t m, uint32_t h, uint32_t* out_trussness,
+                                 uint32_t* out_round, hipStream_t stream) {
+  hoStatus st = check_common(row_ptr, col_idx, n, m, h, out_trussness, (void*)1);
+  if (st != HO_OK) return st;
+  if (m == 0) {
+    t_stats = hoStats{};
+    return HO_OK;
+  }
+  Plan p;
+  const size_t need = noalloc_bytes(n, m, h, &p);
+  if (need == 0) return HO_ERR_INVALID_ARG;
+  if (need > SCRATCH_BYTES) return HO_ERR_WORKSPACE;
+  int dev = 0;
+  HIPCHK(hipGetDevice(&dev));
+  if (dev < 0 || dev >= SCRATCH_MAX_DEVICES) return HO_ERR_INVALID_ARG;
+  std::lock_guard<std::mutex> lk(g_scratch_mu[dev]);
+  void* base = scratch_base(dev);
+  if (!base) return HO_ERR_HIP;
+  const unsigned T = 256;
+  const uintptr_t b = (uintptr_t)base;
+  Dev* dself = (Dev*)b;
+  uint32_t* status = (uint32_t*)(b + up(sizeof(Dev)));
+  Dev d = carve(p, (void*)(b + up(sizeof(Dev)) + up(4ull * HO_STATUS_WORDS)), row_ptr, col_idx,
+                out_trussness, out_round);
+  const RoundGrid g = plain_grid(m, nullptr);
+  d.self = dself;
+  d.status = status;
+  d.nminpart = g.jump;
+  // the array keeps the previous call's contents: every buffer that must
+  // start at a known value is written before it is read
+  hipLaunchKernelGGL(k_fill32, dim3(1), dim3(64), 0, stream, status, (size_t)HO_STATUS_WORDS, 0u);
+  hipLaunchKernelGGL(k_fill32, dim3(grid_for(d.m, T)), dim3(T), 0, stream, d.t, (size_t)d.m, 0u);
+  for (uint32_t j = 1; j <= d.h; ++j)
+    if (d.Dm[j])
+      hipLaunchKernelGGL(k_fill64, dim3(grid_for((size_t)d.n * d.W, T)), dim3(T), 0, stream,
+                         d.Dm[j], (size_t)d.n * d.W, 0ull);
+  HOCHK(run_init(d, d.sup, nullptr, stream));
+  hipLaunchKernelGGL(k_init_rows, dim3(grid_for(d.nnz, T)), dim3(T), 0, stream, d);
+  // the descriptor goes to the device from a host stack copy (staged by the
+  // runtime, so the copy is complete when the call returns)
+  HIPCHK(hipMemcpyAsync(dself, &d, sizeof(Dev), hipMemcpyHostToDevice, stream));
+  hipLaunchKernelGGL(k_post_init, dim3(1), dim3(64), 0, stream, d);
+  HIPCHK(hipGetLastError());
+  Ctl c;
+  HOCHK(read_ctl(d, &c, stream));
+  if (c.err) return HO_ERR_BAD_CSR;
+  hoStats out{};
+  HOCHK(run_rounds_host(d, g, stream, false, out.kernel_ms, out.kernel_launches));
+  HOCHK(read_ctl(d, &c, stream));
+  if (c.err) return HO_ERR_BAD_CSR;
+  if (!c.done) return HO_ERR_INTERNAL;
+  out.rounds = c.r;
+  out.levels = c.levels;
+  out.events = c.events;
+  out.overflows = c.overflows;
+  out.compactions = c.compactions;
   t_stats = out;
   return HO_OK;
 }

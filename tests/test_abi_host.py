@@ -191,3 +191,14 @@ def test_vertex_cap_of_the_ball_rows(ht):
     assert lib.hoTrussDecompose(fake, fake, cap + 1, 5, 2, fake, None, fake, big, None,
                                 None) == -1
     assert lib.hoTrussHSupport(fake, fake, cap + 1, 5, 2, fake, fake, big, None, None) == -1
+
+
+def test_noalloc_size_limit_before_device_work(ht):
+    # the allocation-free entry point has a fixed 256 MiB device array: a graph
+    # whose workspace does not fit is refused before any device work
+    lib = ht.lib
+    fake = C.c_void_p(0x1000)
+    assert lib.hoTrussDecomposeNoAlloc(fake, fake, 60_000, 300_000, 2, fake, fake, None) == -3
+    assert lib.hoTrussDecomposeNoAlloc(fake, fake, 524_289, 5, 2, fake, fake, None) == -1
+    assert lib.hoTrussDecomposeNoAlloc(fake, fake, 10, 5, 0, fake, fake, None) == -1
+    assert lib.hoTrussDecomposeNoAlloc(None, None, 10, 0, 2, None, None, None) == 0
