@@ -380,19 +380,6 @@ __device__ void emit_word_items(const Dev& d, uint32_t j, bool active, uint32_t 
   emit_group<ITEM_WORDS>(d, j, 0, 0, x, z, 0, active ? d.W : 0u);
 }
 
-// Record `cnt` (0..2) events of this lane at level j (all lanes call).
-__device__ void record_events(const Dev& d, uint32_t j, uint32_t p, uint32_t cnt, uint64_t e0,
-                              uint64_t e1) {
-  const uint32_t slot = wave_reserve(&d.ctl->nev[j][p], cnt);
-  const uint32_t cap = (j == 1) ? 2 * d.m + 2 : d.evcap;
-  bool over = false;
-  for (uint32_t i = 0; i < cnt; ++i) {
-    if (slot + i < cap) d.evl[j][p][slot + i] = i ? e1 : e0;
-    else over = true;
-  }
-  if (over) d.ctl->ovf[j][p] = 1;
-}
-
 // ---- K1: level-jump minimum and clearing of overflowed change marks ----
 __global__ void __launch_bounds__(256) k_jump_min(const Dev* __restrict__ devs) {
   const Dev& d = devs[blockIdx.y];
@@ -530,8 +517,11 @@ __global__ void __launch_bounds__(256) k_mark(const Dev* __restrict__ devs) {
       mark_edge(d, rc, valid, valid ? d.R[rc.p][i] : 0, i);
     }
   }
-  // clear the listed change marks of the previous round (distinct bits from
-  // the ones this round sets); overflowed levels were cleared by k_jump_min
+  // clear the listed change marks of the previous round; overflowed levels
+  // were cleared by k_jump_min.  At levels j >= 2 every bit set now is from
+  // the previous round (this round sets its own in k_level, later), so whole
+  // words are zeroed with plain stores; level 1 (h = 1 only) gets this
+  // round's marks in this launch, so its old bits are cleared one by one.
   for (uint32_t j = 1; j <= d.h; ++j) {
     uint64_t* D = d.Dm[j];
     if (!D || c->ovf[j][q]) continue;
@@ -540,7 +530,8 @@ __global__ void __launch_bounds__(256) k_mark(const Dev* __restrict__ devs) {
     for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < ne; i += wstride) {
       const uint64_t xw = E[i];
       const uint32_t x = (uint32_t)(xw >> 32), w = (uint32_t)xw;
-      atomicAnd(&row(D, d.W, x)[w >> 6], ~(1ull << (w & 63)));
+      if (j >= 2) row(D, d.W, x)[w >> 6] = 0;
+      else atomicAnd(&row(D, d.W, x)[w >> 6], ~(1ull << (w & 63)));
     }
   }
 }
@@ -549,6 +540,7 @@ __global__ void __launch_bounds__(256) k_mark(const Dev* __restrict__ devs) {
 constexpr uint32_t LV_THREADS = 256;
 constexpr uint32_t LV_WAVES = LV_THREADS / WAVE;
 constexpr uint32_t LV_CAP = 1024;  // candidate pairs buffered per workgroup
+constexpr uint32_t LV_DENSE = 256; // of those, most tested on bitset rows per flush
 
 // Block-wide exclusive scan of v[0..n) (n <= LV_CAP) into out; returns the total.
 __device__ uint32_t block_scan_cap(const uint32_t* v, uint32_t* out, uint32_t n, uint32_t* wsum) {
@@ -590,8 +582,9 @@ __global__ void __launch_bounds__(LV_THREADS) k_level(const Dev* __restrict__ de
   __shared__ uint32_t cx[LV_CAP], cw[LV_CAP], cb[LV_CAP], cbeg[LV_CAP], cdeg[LV_CAP],
       coff[LV_CAP];
   __shared__ uint32_t cflag[LV_CAP];
-  __shared__ uint32_t cdense[LV_CAP];  // candidates tested by bitset rows (see the flush)
+  __shared__ uint32_t cdense[LV_DENSE];  // candidates tested by bitset rows (see the flush)
   __shared__ uint32_t s_count, s_busy[2], s_wsum[LV_WAVES], s_ndense;
+  __shared__ uint32_t s_wres[LV_WAVES][2], s_bres[2];  // per-wave and workgroup reservations
   __shared__ uint32_t s_stat[5];  // stats mode: items, slots, candidates, probes, drops
   Ctl* c = d.ctl;
   if (c->done) return;
@@ -753,14 +746,14 @@ __global__ void __launch_bounds__(LV_THREADS) k_level(const Dev* __restrict__ de
       uint32_t at = 0;
       if (lane == 0 && bd) at = atomicAdd(&s_ndense, (uint32_t)__popcll(bd));
       at = __shfl(at, 0, WAVE) + (uint32_t)__popcll(bd & ((1ull << lane) - 1));
-      if (dense) {
+      if (dense && at < LV_DENSE) {  // the rest keep their neighbour probes
         cdense[at] = i;
         cdeg[i] = 0;
       }
     }
     __syncthreads();
     const uint32_t total = block_scan_cap(cdeg, coff, n, s_wsum);
-    const uint32_t ndense = s_ndense;
+    const uint32_t ndense = min(s_ndense, LV_DENSE);
     if (counting && threadIdx.x == 0) s_stat[3] += total;
     for (uint32_t pidx = threadIdx.x; pidx < total; pidx += LV_THREADS) {
       uint32_t lo = 0, hi = n;
@@ -811,37 +804,68 @@ __global__ void __launch_bounds__(LV_THREADS) k_level(const Dev* __restrict__ de
         if (w2) atomicOr(&row(d.Dm[j], d.W, w)[x >> 6], bw);
       }
       if (counting && (w1 || w2)) atomicAdd(&s_stat[4], (uint32_t)w1 + (uint32_t)w2);
-      const uint64_t exw = ((uint64_t)x << 32) | w, ewx = ((uint64_t)w << 32) | x;
-      record_events(d, j, rc.p, (uint32_t)w1 + (uint32_t)w2, w1 ? exw : ewx, ewx);
-      // follow-up items of both events with one reservation: the support
-      // update over the row of the event's source (j == h), else the next
-      // level's candidates (y, w) over that row plus (x, w) itself
-      {
-        const uint32_t extra = j == d.h ? 0u : 1u;
-        const uint32_t list = j == d.h ? d.h + 1 : j + 1;
-        uint32_t bx = 0, nx = 0, bw = 0, nw = 0;
-        if (w1) {
-          bx = d.rp[x];
-          nx = row_end(d, x) - bx + extra;
-        }
-        if (w2) {
-          bw = d.rp[w];
-          nw = row_end(d, w) - bw + extra;
-        }
-        const uint32_t c1 = chunks_of(nx), c2 = chunks_of(nw);
-        uint32_t t1, t2;
-        const uint32_t e1 = wave_excl_scan(c1, &t1), e2 = wave_excl_scan(c2, &t2);
-        const uint32_t first = reserve_wave(&d.ctl->nit[list], t1 + t2);
-        if (j == d.h) {
-          // support items carry the slot base of their chunk
-          emit_items_wave<ITEM_SLOTS>(d, list, first, t1, e1, c1, 0, 0, x, w, bx, nx);
-          emit_items_wave<ITEM_SLOTS>(d, list, first + t1, t2, e2, c2, 0, 0, w, x, bw, nw);
-        } else {
-          emit_items_wave<ITEM_ROW>(d, list, first, t1, e1, c1, KIND_B_SLOTS, 1, x, w, bx, nx);
-          emit_items_wave<ITEM_ROW>(d, list, first + t1, t2, e2, c2, KIND_B_SLOTS, 1, w, x, bw,
-                                    nw);
-        }
+      // Follow-up work of both events: the events themselves, and items over
+      // the row of each event's source -- the support update (j == h), else
+      // the next level's candidates (y, w) over that row plus (x, w) itself.
+      // Both lists are reserved once per workgroup: device-scope atomics on
+      // one address serialise, and a large round has thousands of wavefronts
+      // with drops.
+      const uint32_t extra = j == d.h ? 0u : 1u;
+      const uint32_t list = j == d.h ? d.h + 1 : j + 1;
+      uint32_t bx = 0, nx = 0, bw = 0, nw = 0;
+      if (w1) {
+        bx = d.rp[x];
+        nx = row_end(d, x) - bx + extra;
       }
+      if (w2) {
+        bw = d.rp[w];
+        nw = row_end(d, w) - bw + extra;
+      }
+      const uint32_t c1 = chunks_of(nx), c2 = chunks_of(nw);
+      const uint32_t ne = (uint32_t)w1 + (uint32_t)w2;
+      uint32_t t1, t2, te;
+      const uint32_t e1 = wave_excl_scan(c1, &t1), e2 = wave_excl_scan(c2, &t2);
+      const uint32_t ee = wave_excl_scan(ne, &te);
+      if (lane == 0) {
+        s_wres[wave][0] = t1 + t2;
+        s_wres[wave][1] = te;
+      }
+      __syncthreads();
+      if (threadIdx.x == 0) {
+        uint32_t ti = 0, tv = 0;
+        for (uint32_t v = 0; v < LV_WAVES; ++v) {
+          ti += s_wres[v][0];
+          tv += s_wres[v][1];
+        }
+        s_bres[0] = ti ? atomicAdd(&d.ctl->nit[list], ti) : 0u;
+        s_bres[1] = tv ? atomicAdd(&d.ctl->nev[j][rc.p], tv) : 0u;
+      }
+      __syncthreads();
+      uint32_t ifirst = s_bres[0], efirst = s_bres[1];
+      for (uint32_t v = 0; v < wave; ++v) {
+        ifirst += s_wres[v][0];
+        efirst += s_wres[v][1];
+      }
+      {
+        const uint64_t exw = ((uint64_t)x << 32) | w, ewx = ((uint64_t)w << 32) | x;
+        const uint32_t slot = efirst + ee;
+        bool over = false;
+        for (uint32_t k = 0; k < ne; ++k) {
+          if (slot + k < d.evcap) d.evl[j][rc.p][slot + k] = (k || !w1) ? ewx : exw;
+          else over = true;
+        }
+        if (over) d.ctl->ovf[j][rc.p] = 1;
+      }
+      if (j == d.h) {
+        // support items carry the slot base of their chunk
+        emit_items_wave<ITEM_SLOTS>(d, list, ifirst, t1, e1, c1, 0, 0, x, w, bx, nx);
+        emit_items_wave<ITEM_SLOTS>(d, list, ifirst + t1, t2, e2, c2, 0, 0, w, x, bw, nw);
+      } else {
+        emit_items_wave<ITEM_ROW>(d, list, ifirst, t1, e1, c1, KIND_B_SLOTS, 1, x, w, bx, nx);
+        emit_items_wave<ITEM_ROW>(d, list, ifirst + t1, t2, e2, c2, KIND_B_SLOTS, 1, w, x, bw,
+                                  nw);
+      }
+      __syncthreads();  // s_wres and s_bres are reused by the next pass
     }
     __syncthreads();
     for (uint32_t i = threadIdx.x; i < n; i += LV_THREADS) cflag[i] = 0;
@@ -888,60 +912,61 @@ __global__ void __launch_bounds__(256) k_support(const Dev* __restrict__ devs) {
   uint32_t* Rn = d.R[rc.p ^ 1];
   const Item* items = d.itl[list];
   const uint32_t stride = gridDim.x * wpb;
-  // items dealt to workgroups first, then to their waves; software-pipelined:
-  // the next item and its slots (state, neighbour, edge id) load while the
-  // current item's ball words and support atomics are in flight
-  uint32_t it = (threadIdx.x / WAVE) * gridDim.x + blockIdx.x;
-  Item I{0, 0, 0, 0};
-  uint32_t sr = 0, b = 0, e = 0;
-  if (it < nit) {
-    I = items[it];
-    if (lane < meta_len(I.meta)) {
-      const uint32_t q = I.base + lane;
-      sr = d.srem[q];
-      b = d.cix[q];
-      e = d.eid[q];
-    }
-  }
-  while (it < nit) {
-    const uint32_t len = meta_len(I.meta);
-    const bool live = lane < len && sr > rc.r;
-    uint64_t word = 0;
-    if (live) {
-      const size_t o = (size_t)I.y * d.W + (b >> 6);
-      word = Lh[o];
-      if (I.x < b) word |= Dh[o];
-    }
-    const uint32_t nx = it + stride;
-    Item I2{0, 0, 0, 0};
-    uint32_t sr2 = 0, b2 = 0, e2 = 0;
-    if (nx < nit) {
-      I2 = items[nx];
-      if (lane < meta_len(I2.meta)) {
-        const uint32_t q = I2.base + lane;
-        sr2 = d.srem[q];
-        b2 = d.cix[q];
-        e2 = d.eid[q];
+  // Items are dealt to workgroups first, then to their waves.  Each wave
+  // takes two items per step (its items it and it + stride), and the step's
+  // successors and their slots (state, neighbour, edge id) load while the
+  // current pair's ball words and support atomics are in flight: more memory
+  // operations outstanding per wave than one item's dependent chain.
+  struct Slot {
+    Item I;
+    uint32_t sr, b, e;
+  };
+  auto fetch = [&](uint32_t i, Slot& S) {
+    S.I = Item{0, 0, 0, 0};
+    S.sr = S.b = S.e = 0;
+    if (i < nit) {
+      S.I = items[i];
+      if (lane < meta_len(S.I.meta)) {
+        const uint32_t q = S.I.base + lane;
+        S.sr = d.srem[q];
+        S.b = d.cix[q];
+        S.e = d.eid[q];
       }
     }
-    const bool hit = live && ((word >> (b & 63)) & 1ull);
-    bool push = false;
-    if (hit) push = atomicSub(&d.sup[e], 1u) == rc.k - 1;
-    const uint32_t slot = wave_reserve(&c->nPush, push ? 1u : 0u);
-    if (push) Rn[slot] = e;
+  };
+  // w in b's old ball when the event's source a < b, in its new ball when a > b
+  auto hit_of = [&](const Slot& S) -> bool {
+    if (!(lane < meta_len(S.I.meta) && S.sr > rc.r)) return false;
+    const size_t o = (size_t)S.I.y * d.W + (S.b >> 6);
+    uint64_t word = Lh[o];
+    if (S.I.x < S.b) word |= Dh[o];
+    return (word >> (S.b & 63)) & 1ull;
+  };
+  uint32_t it = (threadIdx.x / WAVE) * gridDim.x + blockIdx.x;
+  Slot A, B;
+  fetch(it, A);
+  fetch(it + stride, B);
+  while (it < nit) {
+    const bool ha = hit_of(A), hb = hit_of(B);
+    Slot A2, B2;
+    fetch(it + 2 * stride, A2);
+    fetch(it + 3 * stride, B2);
+    const bool pa = ha && atomicSub(&d.sup[A.e], 1u) == rc.k - 1;
+    const bool pb = hb && atomicSub(&d.sup[B.e], 1u) == rc.k - 1;
+    const uint32_t slot = wave_reserve(&c->nPush, (uint32_t)pa + (uint32_t)pb);
+    if (pa) Rn[slot] = A.e;
+    if (pb) Rn[slot + (uint32_t)pa] = B.e;
     if (counting) {
-      const uint32_t hits = (uint32_t)__popcll(__ballot(hit));
+      const uint32_t hits = (uint32_t)__popcll(__ballot(ha)) + (uint32_t)__popcll(__ballot(hb));
       if (lane == 0) {
-        atomicAdd(&s_stat[0], 1u);
-        atomicAdd(&s_stat[1], len);
+        atomicAdd(&s_stat[0], 1u + (it + stride < nit ? 1u : 0u));
+        atomicAdd(&s_stat[1], meta_len(A.I.meta) + meta_len(B.I.meta));
         atomicAdd(&s_stat[2], hits);
       }
     }
-    I = I2;
-    sr = sr2;
-    b = b2;
-    e = e2;
-    it = nx;
+    A = A2;
+    B = B2;
+    it += 2 * stride;
   }
   if (counting) {
     __syncthreads();
