@@ -115,9 +115,11 @@ typedef struct {
     uint64_t compactions;   /* adjacency compactions (live slots moved to the row fronts) */
     double   device_ms;     /* device time of the whole call (HIP events)          */
     /* HO_FLAG_STATS only: summed HIP-event time and launch count per kernel kind:
-     * 0 initial h-support, 1 level-jump minimum, 2 peel/mark, 3 ball-change
-     * events (all levels), 4 support update, 5 end of round.  Stats mode drives
-     * the rounds from the host, so device_ms is then not the production time. */
+     * 0 initial h-support, 1 unused (the level-jump minimum is computed by the
+     * end-of-round kernel), 2 peel/mark, 3 ball-change events (all levels),
+     * 4 support update, 5 end of round with the next round's level-jump
+     * minimum.  Stats mode drives the rounds from the host, so device_ms is
+     * then not the production time. */
     double   kernel_ms[6];
     uint64_t kernel_launches[6];
     /* HO_FLAG_STATS only: work done by the chunked kernels.  Ball-change

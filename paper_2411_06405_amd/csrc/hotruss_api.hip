@@ -178,7 +178,7 @@ Dev carve(const Plan& p, void* ws, const uint32_t* rp, const uint32_t* ci, uint3
   d.nnz = (uint32_t)(2 * p.m);
   d.evcap = p.evcap;
   d.itcap = p.itcap;
-  d.nminpart = 1;  // set by the engine to its k_jump_min grid width
+  d.nminpart = 1;  // set by the engine to the grid width of its minimum kernels
   d.ctl = (Ctl*)at(p.off_ctl);
   d.eid = (uint32_t*)at(p.off_eid);
   d.eu = (uint32_t*)at(p.off_eu);
@@ -310,7 +310,7 @@ RoundGrid plain_grid(uint64_t m, const hoTuning* tune) {
   const unsigned wide = tune && tune->grid_blocks ? tune->grid_blocks : (unsigned)num_cu() * 8;
   g.jump = std::min<unsigned>(MIN_PART, grid_for(m, 256, 4));
   g.mark = std::max(1u, std::min(wide, grid_for(m, 256)));
-  g.level = std::min<unsigned>(wide, STAT_GRID);
+  g.level = std::max(1u, std::min<unsigned>(wide, STAT_GRID) * 256 / LV_THREADS);
   g.support = std::min<unsigned>(wide, STAT_GRID);
   return g;
 }
@@ -322,7 +322,7 @@ RoundGrid batch_grid(uint32_t slots, const hoTuning* tune) {
   // step wait on the slot with the largest round.
   const unsigned total = tune && tune->grid_blocks ? tune->grid_blocks : (unsigned)num_cu() * 64;
   const unsigned per = std::max(4u, std::min(256u, total / std::max(1u, slots)));
-  RoundGrid g{std::min<unsigned>(MIN_PART, per), per, per, per};
+  RoundGrid g{std::min<unsigned>(MIN_PART, per), per, std::max(1u, per * 256 / LV_THREADS), per};
   return g;
 }
 
@@ -331,12 +331,11 @@ enum { KT_SUPINIT = 0, KT_JUMP, KT_MARK, KT_LEVEL, KT_SUPPORT, KT_ADVANCE, KT_N 
 
 void launch_step(const Dev* devs, uint32_t S, uint32_t hmax, const RoundGrid& g, hipStream_t s) {
   const unsigned T = 256;
-  hipLaunchKernelGGL(k_jump_min, dim3(g.jump, S), dim3(T), 0, s, devs);
   hipLaunchKernelGGL(k_mark, dim3(g.mark, S), dim3(T), 0, s, devs);
   for (uint32_t j = 2; j <= hmax; ++j)
     hipLaunchKernelGGL(k_level, dim3(g.level, S), dim3(LV_THREADS), 0, s, devs, j);
   hipLaunchKernelGGL(k_support, dim3(g.support, S), dim3(T), 0, s, devs);
-  hipLaunchKernelGGL(k_advance, dim3(1, S), dim3(64), 0, s, devs);
+  hipLaunchKernelGGL(k_end, dim3(g.jump, S), dim3(T), 0, s, devs);
 }
 
 // Compact again once a tenth of the live edges have been peeled since the
@@ -472,7 +471,7 @@ hoStatus steps_host(const Dev& d, const RoundGrid& g, hipStream_t s, uint32_t fr
     hipLaunchKernelGGL(k_acct_reset, dim3(1), dim3(64), 0, s, dp);
   }
   HOCHK(tm.begin(s));
-  hipLaunchKernelGGL(k_advance, dim3(1), dim3(64), 0, s, dp);
+  hipLaunchKernelGGL(k_end, dim3(g.jump), dim3(T), 0, s, dp);
   HOCHK(tm.end(s, KT_ADVANCE));
   HIPCHK(hipGetLastError());
   return HO_OK;
@@ -784,6 +783,7 @@ class Engine {
     dev_h[i] = d;
     HIPCHK(hipMemcpyAsync(d.self, &dev_h[i], sizeof(Dev), hipMemcpyHostToDevice, s));
     hipLaunchKernelGGL(k_post_init, dim3(1), dim3(64), 0, s, d);
+    hipLaunchKernelGGL(k_first_min, dim3(g.jump), dim3(T), 0, s, d.self);
     HIPCHK(hipGetLastError());
     return HO_OK;
   }
@@ -1012,9 +1012,6 @@ hoStatus run_rounds_host(const Dev& d, const RoundGrid& g, hipStream_t s, bool t
     double kms0[KT_N];
     for (int i = 0; i < KT_N; ++i) kms0[i] = timed ? kms[i] : 0.0;
     const Ctl before = c;
-    if ((st = tm.begin(s)) != HO_OK) break;
-    hipLaunchKernelGGL(k_jump_min, dim3(g.jump), dim3(T), 0, s, dp);
-    if ((st = tm.end(s, KT_JUMP)) != HO_OK) break;
     if ((st = tm.begin(s)) != HO_OK) break;
     hipLaunchKernelGGL(k_mark, dim3(g.mark), dim3(T), 0, s, dp);
     if ((st = tm.end(s, KT_MARK)) != HO_OK) break;
@@ -1300,6 +1297,7 @@ hoStatus hoTrussDecomposeNoAlloc(const uint32_t* row_ptr, const uint32_t* col_id
   // runtime, so the copy is complete when the call returns)
   HIPCHK(hipMemcpyAsync(dself, &d, sizeof(Dev), hipMemcpyHostToDevice, stream));
   hipLaunchKernelGGL(k_post_init, dim3(1), dim3(64), 0, stream, d);
+  hipLaunchKernelGGL(k_first_min, dim3(g.jump), dim3(T), 0, stream, dself);
   HIPCHK(hipGetLastError());
   Ctl c;
   HOCHK(read_ctl(d, &c, stream));

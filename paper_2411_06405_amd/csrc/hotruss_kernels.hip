@@ -42,6 +42,7 @@ __global__ void k_init_ctl(Ctl* ctl, uint32_t m) {
     uint32_t* w = reinterpret_cast<uint32_t*>(ctl);
     for (uint32_t i = 0; i < sizeof(Ctl) / 4; ++i) w[i] = 0;
     ctl->k = 2;
+    ctl->jump = 1;  // nothing pushed yet: the first round jumps to min sup + 2
     ctl->live = m;
     ctl->levels = 0;
     ctl->done = (m == 0);
@@ -285,8 +286,7 @@ __global__ void __launch_bounds__(256) k_support_init(Dev d, uint32_t* __restric
 
 // ============================================================ peel rounds
 // A round runs as a fixed kernel sequence (captured once into a HIP graph and
-// replayed): k_jump_min, k_mark, k_level(j) for j = 2..h, k_support,
-// k_advance.  Every kernel reads the control block and returns at once when
+// replayed): k_mark, k_level(j) for j = 2..h, k_support, k_end.  Every kernel reads the control block and returns at once when
 // the decomposition is finished, so a graph may run past the last round.
 
 struct RoundCtx {
@@ -380,49 +380,44 @@ __device__ void emit_word_items(const Dev& d, uint32_t j, bool active, uint32_t 
   emit_group<ITEM_WORDS>(d, j, 0, 0, x, z, 0, active ? d.W : 0u);
 }
 
-// ---- K1: level-jump minimum and clearing of overflowed change marks ----
-__global__ void __launch_bounds__(256) k_jump_min(const Dev* __restrict__ devs) {
-  const Dev& d = devs[blockIdx.y];
+// ---- level-jump minimum ----------------------------------------------------
+// Per-workgroup minima of the live edges' supports (read by k_mark of a round
+// that starts with a level jump).  Computed by the end-of-round kernel of the
+// previous round, when every support of that round is final, and once after
+// the initial pass.
+__device__ void jump_partials(const Dev& d) {
   __shared__ uint32_t smin[4];
-  const Ctl* c = d.ctl;
-  if (c->done || c->halt) return;
-  const uint32_t p = c->r & 1, q = p ^ 1;
-  if (blockIdx.x == 0 && threadIdx.x == 0) d.ctl->jump = (c->nR == 0);
-  if (c->nR == 0) {
-    // four edges per thread in flight: both loads unconditional
-    uint32_t mn = 0xffffffffu;
-    const uint32_t stride = gridDim.x * blockDim.x;
-    uint32_t e = blockIdx.x * blockDim.x + threadIdx.x;
-    for (; e + 3 * stride < d.m; e += 4 * stride) {
-      uint32_t tv[4], sv[4];
+  // four edges per thread in flight: both loads unconditional
+  uint32_t mn = 0xffffffffu;
+  const uint32_t stride = gridDim.x * blockDim.x;
+  uint32_t e = blockIdx.x * blockDim.x + threadIdx.x;
+  for (; e + 3 * stride < d.m; e += 4 * stride) {
+    uint32_t tv[4], sv[4];
 #pragma unroll
-      for (uint32_t u = 0; u < 4; ++u) {
-        tv[u] = d.t[e + u * stride];
-        sv[u] = d.sup[e + u * stride];
-      }
+    for (uint32_t u = 0; u < 4; ++u) {
+      tv[u] = d.t[e + u * stride];
+      sv[u] = d.sup[e + u * stride];
+    }
 #pragma unroll
-      for (uint32_t u = 0; u < 4; ++u)
-        if (tv[u] == 0) mn = min(mn, sv[u]);
-    }
-    for (; e < d.m; e += stride) {
-      const uint32_t tv = d.t[e], sv = d.sup[e];
-      if (tv == 0) mn = min(mn, sv);
-    }
-    mn = wave_min(mn);
-    if (lane_id() == 0) smin[threadIdx.x / WAVE] = mn;
-    __syncthreads();
-    if (threadIdx.x == 0)
-      d.minpart[blockIdx.x] = min(min(smin[0], smin[1]), min(smin[2], smin[3]));
+    for (uint32_t u = 0; u < 4; ++u)
+      if (tv[u] == 0) mn = min(mn, sv[u]);
   }
-  // change marks of a previous round whose event list overflowed
-  for (uint32_t j = 2; j <= d.h; ++j) {
-    if (!c->ovf[j][q]) continue;
-    uint64_t* D = d.Dm[j];
-    const size_t cnt = (size_t)d.n * d.W;
-    for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < cnt;
-         i += (size_t)gridDim.x * blockDim.x)
-      D[i] = 0;
+  for (; e < d.m; e += stride) {
+    const uint32_t tv = d.t[e], sv = d.sup[e];
+    if (tv == 0) mn = min(mn, sv);
   }
+  mn = wave_min(mn);
+  if (lane_id() == 0) smin[threadIdx.x / WAVE] = mn;
+  __syncthreads();
+  if (threadIdx.x == 0)
+    d.minpart[blockIdx.x] = min(min(smin[0], smin[1]), min(smin[2], smin[3]));
+}
+
+// After the initial pass: the first round starts with a level jump.
+__global__ void __launch_bounds__(256) k_first_min(const Dev* __restrict__ devs) {
+  const Dev& d = devs[blockIdx.y];
+  if (d.ctl->done || d.ctl->err) return;
+  jump_partials(d);
 }
 
 // ---- K2: peel R (level jump: collect it first), level-1 events, items ----
@@ -517,11 +512,19 @@ __global__ void __launch_bounds__(256) k_mark(const Dev* __restrict__ devs) {
       mark_edge(d, rc, valid, valid ? d.R[rc.p][i] : 0, i);
     }
   }
-  // clear the listed change marks of the previous round; overflowed levels
-  // were cleared by k_jump_min.  At levels j >= 2 every bit set now is from
+  // clear the change marks of the previous round: the whole array of a level
+  // whose event list overflowed, else the listed events.  At levels j >= 2 every bit set now is from
   // the previous round (this round sets its own in k_level, later), so whole
   // words are zeroed with plain stores; level 1 (h = 1 only) gets this
   // round's marks in this launch, so its old bits are cleared one by one.
+  for (uint32_t j = 2; j <= d.h; ++j) {
+    if (!c->ovf[j][q]) continue;
+    uint64_t* D = d.Dm[j];
+    const size_t cnt = (size_t)d.n * d.W;
+    for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < cnt;
+         i += (size_t)gridDim.x * blockDim.x)
+      D[i] = 0;
+  }
   for (uint32_t j = 1; j <= d.h; ++j) {
     uint64_t* D = d.Dm[j];
     if (!D || c->ovf[j][q]) continue;
@@ -537,14 +540,18 @@ __global__ void __launch_bounds__(256) k_mark(const Dev* __restrict__ devs) {
 }
 
 // ---- K3: ball-change events at level j >= 2 ----------------------------
-constexpr uint32_t LV_THREADS = 256;
+// 16 wavefronts per workgroup: the drop phase reserves list space once per
+// workgroup on device-wide counters (same-address atomics serialise at about
+// 11 ns each), so fewer, larger workgroups mean fewer of them, and a hub
+// pair's witness probes spread over 1,024 threads
+constexpr uint32_t LV_THREADS = 1024;
 constexpr uint32_t LV_WAVES = LV_THREADS / WAVE;
 constexpr uint32_t LV_CAP = 1024;  // candidate pairs buffered per workgroup
 constexpr uint32_t LV_DENSE = 256; // of those, most tested on bitset rows per flush
 
 // Block-wide exclusive scan of v[0..n) (n <= LV_CAP) into out; returns the total.
 __device__ uint32_t block_scan_cap(const uint32_t* v, uint32_t* out, uint32_t n, uint32_t* wsum) {
-  const uint32_t per = LV_CAP / LV_THREADS;  // 4 entries per thread
+  const uint32_t per = LV_CAP / LV_THREADS;  // entries per thread
   const uint32_t b0 = threadIdx.x * per;
   uint32_t loc[per];
   uint32_t s = 0;
@@ -755,15 +762,32 @@ __global__ void __launch_bounds__(LV_THREADS) k_level(const Dev* __restrict__ de
     const uint32_t total = block_scan_cap(cdeg, coff, n, s_wsum);
     const uint32_t ndense = min(s_ndense, LV_DENSE);
     if (counting && threadIdx.x == 0) s_stat[3] += total;
-    for (uint32_t pidx = threadIdx.x; pidx < total; pidx += LV_THREADS) {
-      uint32_t lo = 0, hi = n;
-      while (hi - lo > 1) {
-        const uint32_t mid = (lo + hi) >> 1;
-        if (coff[mid] <= pidx) lo = mid; else hi = mid;
+    // four probes per thread in flight: owners found in LDS first, then all
+    // slot loads, then all ball-word loads
+    constexpr uint32_t PU = 4;
+    for (uint32_t p0 = threadIdx.x; p0 < total; p0 += PU * LV_THREADS) {
+      uint32_t own[PU], q[PU], sr[PU], y[PU];
+      bool act[PU];
+#pragma unroll
+      for (uint32_t u = 0; u < PU; ++u) {
+        const uint32_t pidx = p0 + u * LV_THREADS;
+        uint32_t lo = 0, hi = n;
+        while (hi - lo > 1) {
+          const uint32_t mid = (lo + hi) >> 1;
+          if (coff[mid] <= pidx) lo = mid; else hi = mid;
+        }
+        own[u] = lo;
+        act[u] = pidx < total && !cflag[lo];
+        q[u] = cbeg[lo] + (pidx - coff[lo]);
       }
-      if (cflag[lo]) continue;
-      const uint32_t q = cbeg[lo] + (pidx - coff[lo]);
-      if (d.srem[q] > rc.r && getbit(Lp, d.W, cb[lo], d.cix[q])) cflag[lo] = 1;
+#pragma unroll
+      for (uint32_t u = 0; u < PU; ++u) {
+        sr[u] = act[u] ? d.srem[q[u]] : 0u;
+        y[u] = act[u] ? d.cix[q[u]] : 0u;
+      }
+#pragma unroll
+      for (uint32_t u = 0; u < PU; ++u)
+        if (act[u] && sr[u] > rc.r && getbit(Lp, d.W, cb[own[u]], y[u])) cflag[own[u]] = 1;
     }
     for (uint32_t k = wave; k < ndense; k += LV_WAVES) {
       const uint32_t i = cdense[k];
@@ -995,16 +1019,29 @@ __global__ void k_stats_fold(const Dev* __restrict__ dp, uint32_t first, uint32_
 }
 
 // ---- K5: end of round ------------------------------------------------------
-__global__ void k_advance(const Dev* __restrict__ devs) {
+// One thread closes the round (counters, next round's peel set and level-jump
+// flag).  When the round pushed no edge, the next round starts with a level
+// jump, and every workgroup computes its share of the live minimum now.  A
+// workgroup may read the push count after the closing thread reset it: it
+// then computes a minimum that nobody reads, which is harmless, and it never
+// skips one that is needed (the count is only ever reset to zero).
+__global__ void __launch_bounds__(256) k_end(const Dev* __restrict__ devs) {
   const Dev& d = devs[blockIdx.y];
-  if (blockIdx.x != 0 || threadIdx.x != 0) return;
   Ctl* c = d.ctl;
-  if (c->done || c->halt) return;
+  // one decision per workgroup, taken before its closing thread (workgroup 0)
+  // changes anything, so that every thread of it takes the same branch
+  __shared__ uint32_t s_mode;  // 0 close only, 1 minimum and close, 2 nothing
+  if (threadIdx.x == 0) s_mode = (c->done || c->halt) ? 2u : (c->nPush == 0 ? 1u : 0u);
+  __syncthreads();
+  const uint32_t mode = s_mode;
+  if (mode == 2) return;
+  if (mode == 1) jump_partials(d);
+  if (blockIdx.x != 0 || threadIdx.x != 0) return;
   const uint32_t p = c->r & 1, q = p ^ 1;
   c->nev[1][p] = 2 * c->nR;  // level-1 events: both directions of every peeled edge
   c->events += c->nev[d.h][p];
   for (uint32_t j = 1; j <= d.h; ++j) c->levents[j] += c->nev[j][p];
-  c->jump = 0;
+  c->jump = c->nPush == 0;
   uint32_t any = 0;
   for (uint32_t j = 1; j <= d.h; ++j) {
     any |= c->ovf[j][p];
