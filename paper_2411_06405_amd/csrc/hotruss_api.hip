@@ -35,7 +35,7 @@ struct Plan {
   size_t off_ctl, off_eid, off_eu, off_ev, off_s1, off_s2, off_srem, off_upcnt, off_upoff,
       off_scan, off_minpart, off_sup, off_rho, off_R0, off_R1, off_L[HMAX + 1],
       off_Dm[HMAX + 1], off_evl[HMAX + 1][2], off_itl[HMAX + 2], off_cix, off_len, off_tci,
-      off_teid, off_acct;
+      off_teid, off_acct, off_ce;
   size_t total = 0;
 };
 
@@ -90,6 +90,7 @@ bool make_plan(uint32_t n, uint64_t m, uint32_t h, const hoTuning* tune, bool fu
   p.off_R0 = take(full ? 4 * m + 4 : 0);
   p.off_R1 = take(full ? 4 * m + 4 : 0);
   p.off_acct = take(full ? 6 * (4 * (size_t)n + 4) : 0);  // stats-mode work count
+  p.off_ce = take(full ? 16 * m + 8 : 0);
   for (uint32_t j = 0; j <= HMAX; ++j) {
     p.off_L[j] = p.off_Dm[j] = 0;
     p.off_evl[j][0] = p.off_evl[j][1] = 0;
@@ -134,6 +135,7 @@ bool make_topo_plan(uint32_t n, uint64_t m, Plan* P, size_t* off_cc) {
   p.off_sup = take(4 * m + 4);
   p.off_rho = p.off_R0 = p.off_R1 = p.off_cix = p.off_len = p.off_tci = p.off_teid = 0;
   p.off_acct = 0;
+  p.off_ce = 0;
   for (uint32_t j = 0; j <= HMAX; ++j) {
     p.off_L[j] = p.off_Dm[j] = 0;
     p.off_evl[j][0] = p.off_evl[j][1] = 0;
@@ -204,6 +206,7 @@ Dev carve(const Plan& p, void* ws, const uint32_t* rp, const uint32_t* ci, uint3
     d.len = (uint32_t*)at(p.off_len);
     d.tci = (uint32_t*)at(p.off_tci);
     d.teid = (uint32_t*)at(p.off_teid);
+    d.ce = (uint64_t*)at(p.off_ce);
     uint32_t* acct = (uint32_t*)at(p.off_acct);
     const size_t na = (size_t)p.n + 1;
     d.acct_ball = acct;

@@ -8,6 +8,7 @@ namespace hotruss {
 
 constexpr uint32_t HMAX = 16;            // largest hop threshold with its own ball level
 constexpr uint32_t ALIVE = 0xffffffffu;  // srem value of a slot whose edge is still in S
+constexpr uint32_t SLOT_GONE = 0x80000000u;  // in the low word of ce: the slot's edge is peeled
 constexpr int WAVE = 64;
 constexpr uint32_t CHUNK = 64;           // slots (or bitset words) per work item
 constexpr uint32_t MIN_PART = 1024;      // partial-minimum slots of the level-jump reduction
@@ -101,6 +102,10 @@ struct Dev {
   uint32_t* len;        // active slots per row [n]
   uint32_t* tci;        // compaction staging: column ids [2m]
   uint32_t* teid;       // compaction staging: edge ids [2m]
+  // The support update's view of a slot, one 8-byte load: low word the
+  // neighbour id with SLOT_GONE set once the edge is peeled, high word the
+  // edge id [2m] (same row layout as cix)
+  uint64_t* ce;
   uint32_t* up_cnt;     // per row: neighbours above the row vertex [n]
   uint32_t* up_off;     // exclusive prefix sum of up_cnt [n]
   uint32_t* scan_tmp;   // block sums for the scan
@@ -129,6 +134,10 @@ struct Dev {
 };
 
 __device__ __forceinline__ uint32_t lane_id() { return threadIdx.x & (WAVE - 1); }
+
+__device__ __forceinline__ uint64_t slot_word(uint32_t e, uint32_t y, bool gone) {
+  return ((uint64_t)e << 32) | y | (gone ? SLOT_GONE : 0u);
+}
 
 // End of row x's active slots (round kernels).
 __device__ __forceinline__ uint32_t row_end(const Dev& d, uint32_t x) { return d.rp[x] + d.len[x]; }

@@ -426,10 +426,13 @@ __device__ void mark_edge(const Dev& d, const RoundCtx& rc, bool valid, uint32_t
   if (valid) {
     d.t[e] = rc.k;
     d.rho[e] = rc.r;
-    d.srem[d.s1[e]] = rc.r;
-    d.srem[d.s2[e]] = rc.r;
+    const uint32_t q1 = d.s1[e], q2 = d.s2[e];
+    d.srem[q1] = rc.r;
+    d.srem[q2] = rc.r;
     a = d.eu[e];
     b = d.ev[e];
+    d.ce[q1] = slot_word(e, b, true);
+    d.ce[q2] = slot_word(e, a, true);
     atomicAnd(&row(d.L[1], d.W, a)[b >> 6], ~(1ull << (b & 63)));
     atomicAnd(&row(d.L[1], d.W, b)[a >> 6], ~(1ull << (a & 63)));
     if (d.h == 1) {
@@ -941,26 +944,28 @@ __global__ void __launch_bounds__(256) k_support(const Dev* __restrict__ devs) {
   // successors and their slots (state, neighbour, edge id) load while the
   // current pair's ball words and support atomics are in flight: more memory
   // operations outstanding per wave than one item's dependent chain.
+  // a slot is one 8-byte word: neighbour b (with SLOT_GONE once the edge is
+  // peeled, i.e. not alive after this round) and edge id e
   struct Slot {
     Item I;
-    uint32_t sr, b, e;
+    uint32_t b, e;
   };
   auto fetch = [&](uint32_t i, Slot& S) {
     S.I = Item{0, 0, 0, 0};
-    S.sr = S.b = S.e = 0;
+    S.b = SLOT_GONE;
+    S.e = 0;
     if (i < nit) {
       S.I = items[i];
       if (lane < meta_len(S.I.meta)) {
-        const uint32_t q = S.I.base + lane;
-        S.sr = d.srem[q];
-        S.b = d.cix[q];
-        S.e = d.eid[q];
+        const uint64_t w = d.ce[S.I.base + lane];
+        S.b = (uint32_t)w;
+        S.e = (uint32_t)(w >> 32);
       }
     }
   };
   // w in b's old ball when the event's source a < b, in its new ball when a > b
   auto hit_of = [&](const Slot& S) -> bool {
-    if (!(lane < meta_len(S.I.meta) && S.sr > rc.r)) return false;
+    if (S.b & SLOT_GONE) return false;
     const size_t o = (size_t)S.I.y * d.W + (S.b >> 6);
     uint64_t word = Lh[o];
     if (S.I.x < S.b) word |= Dh[o];
@@ -1264,6 +1269,7 @@ __global__ void __launch_bounds__(256) k_compact_commit(Dev d) {
       d.cix[q] = y;
       d.eid[q] = e;
       d.srem[q] = ALIVE;
+      d.ce[q] = slot_word(e, y, false);
       if (y > x) d.s1[e] = q;
       else d.s2[e] = q;
     }
@@ -1274,8 +1280,10 @@ __global__ void __launch_bounds__(256) k_compact_commit(Dev d) {
 __global__ void k_init_rows(Dev d) {
   if (d.ctl->err) return;
   for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < d.nnz;
-       i += (size_t)gridDim.x * blockDim.x)
+       i += (size_t)gridDim.x * blockDim.x) {
     d.cix[i] = d.ci[i];
+    d.ce[i] = slot_word(d.eid[i], d.ci[i], false);
+  }
   for (uint32_t x = blockIdx.x * blockDim.x + threadIdx.x; x < d.n; x += gridDim.x * blockDim.x)
     d.len[x] = d.rp[x + 1] - d.rp[x];
 }
