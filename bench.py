@@ -61,7 +61,7 @@ WORKLOADS = {
                          "Chung-Lu n=100000 avg_deg=10 gamma=2.5 seed=1, h=1 (classical truss)"),
 }
 
-CPU_SAMPLE_N = 4000  # Chung-Lu sample the oracle decomposes completely (about 10-30 s)
+CPU_SAMPLE_N = 6000  # Chung-Lu sample the oracle decomposes completely (about 10-30 s)
 
 # Algorithmic bytes per unit of work of the two chunked round kernels (each
 # access counted at its natural size, not as cache lines):
@@ -69,8 +69,10 @@ CPU_SAMPLE_N = 4000  # Chung-Lu sample the oracle decomposes completely (about 1
 #     tested pair 32 B (ball bit word, two row extents, (j-1)-ball word);
 #     witness probe 16 B (srem, col_idx, ball word); dropped pair 48 B (two
 #     ball-bit atomics, change-mark atomic, event record, follow-up items)
-#   support update: work item 16 B; adjacency slot 20 B (srem, col_idx,
-#     edge id, ball word); lost common neighbour 8 B (support atomic)
+#   support update: work item 16 B; adjacency slot 20 B (the packed
+#     neighbour and edge id word, the event target's ball word, and its
+#     change-mark word for the half of the slots whose source is the smaller
+#     endpoint); lost common neighbour 8 B (support atomic)
 LEVEL_BYTES = {"level_items": 16, "level_slots": 8, "level_candidates": 32,
                "level_probes": 16, "level_drops": 48}
 SUPPORT_BYTES = {"support_items": 16, "support_slots": 20, "support_hits": 8}
@@ -170,8 +172,8 @@ def cpu_baseline(workload: str):
         desc = f"Chung-Lu n={CPU_SAMPLE_N} (same avg_deg/gamma/seed)"
         desc1 = f"Chung-Lu n={CPU_SAMPLE_N // 2}"
     elif workload.startswith("rmat"):
-        g, g1 = W.d3(scale=10), W.d3(scale=9)
-        desc = "R-MAT scale 10 (same a,b,c,d, ef, seed)"
+        g, g1 = W.d3(scale=11), W.d3(scale=9)
+        desc = "R-MAT scale 11 (same a,b,c,d, ef, seed)"
         desc1 = "R-MAT scale 9"
     else:
         g = g1 = make()

@@ -29,6 +29,15 @@ def test_peel_roofline_arithmetic():
     assert r["traffic"] is None
 
 
+def test_support_roofline_arithmetic():
+    st = _peel_stats()
+    st["kernel_ms"]["support_update"] = 80.0
+    r = bench.roofline_from_stats(st, "no_such_workload")
+    alg = 6 * 16 + 7 * 20 + 8 * 8
+    assert r["kernel"] == "k_support"
+    assert r["alg_bytes_per_launch"] == pytest.approx(alg / 100)
+
+
 def test_hindex_roofline_arithmetic():
     st = {"rounds": 4,
           "kernel_ms": {"a": 1.0, "b": 2.0, "c": 8.0, "d": 0.5},
