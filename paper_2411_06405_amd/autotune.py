@@ -11,7 +11,10 @@ h-support of every edge) has three knobs that change speed, never results:
 
 ``autotune`` times ``hoTrussHSupport`` (which runs exactly that pass) on the
 caller's graph for each candidate setting, one knob group at a time, and
-keeps the fastest.  Results are cached in a JSON file keyed by the device
+keeps the fastest.  ``autotune_rounds`` adds the knob of the peel rounds,
+which take almost all of a decomposition's time: ``grid_blocks``, the
+workgroups of the round kernels (the ball-change kernel uses a quarter as
+many, of four times the size), timed on whole decompositions.  Results are cached in a JSON file keyed by the device
 name and a bucket of the graph's shape (vertices, average degree, degree
 skew, h), so graphs of a similar shape reuse a measurement.  The timing runs
 through the C ABI like any other call; nothing here computes on the CPU.
@@ -30,6 +33,7 @@ import numpy as np
 DENSE_THRESHOLDS = (4, 32, 256, 1 << 30)   # 1 << 30: never bottom-up
 WIDTHS = (64, 128)
 EDGES_PER_WAVE = (1, 4, 16)
+GRID_PER_CU = (4, 8, 16)   # round-kernel workgroups per CU
 DEFAULT_CACHE = Path(os.environ.get("HOTRUSS_TUNE_CACHE",
                                     Path.home() / ".cache" / "hotruss_autotune.json"))
 
@@ -65,6 +69,17 @@ def search(time_fn: Callable[[dict], float], repeats: int = 3) -> dict:
              for wb in WIDTHS for ew in EDGES_PER_WAVE}
     base["word_bits"], base["edges_per_wave"] = choose(pairs)
     return base
+
+
+def search_rounds(time_fn: Callable[[dict], float], base: dict, num_cu: int,
+                  repeats: int = 1) -> dict:
+    """The round kernels' grid width, on top of the initial-pass setting
+    `base`: time_fn(tune) returns seconds for one whole decomposition."""
+    timings = {}
+    for per in GRID_PER_CU:
+        tune = dict(base, grid_blocks=per * num_cu)
+        timings[per * num_cu] = min(time_fn(tune) for _ in range(repeats))
+    return dict(base, grid_blocks=choose(timings))
 
 
 class Cache:
@@ -148,3 +163,42 @@ def autotune_batch(graphs: Iterable, hs, device="cuda", cache=None, sample: int 
         votes[k] = votes.get(k, 0) + 1
     best = max(votes.items(), key=lambda kv: kv[1])[0]
     return dict(best)
+
+
+def autotune_rounds(row_ptr, col_idx, n: int, h: int, device="cuda", cache=None,
+                    refresh=False, repeats: int = 1) -> dict:
+    """Initial-pass knobs (``autotune``) plus the round kernels' grid width,
+    chosen by timing whole decompositions of this graph (use a graph that
+    decomposes in seconds, or a smaller one of the same shape)."""
+    import torch
+
+    from . import _lib
+    base = autotune(row_ptr, col_idx, n, h, device=device, cache=cache, refresh=refresh)
+    rp = _lib._dev_u32(row_ptr, device)
+    ci = _lib._dev_u32(col_idx, device)
+    m = ci.numel() // 2
+    if m == 0:
+        return base
+    deg = (rp[1:] - rp[:-1])
+    max_deg = int(deg.max().item()) if n else 0
+    dev = torch.device(device)
+    name = torch.cuda.get_device_name(dev)
+    key = shape_key(name, n, m, h, max_deg) + "|rounds"
+    c = cache if isinstance(cache, Cache) else Cache(cache)
+    if not refresh:
+        hit = c.get(key)
+        if hit is not None:
+            return hit
+    ws = _lib.alloc_workspace(n, m, h, device=device)
+    stream = torch.cuda.current_stream(dev)
+
+    def time_fn(tune: dict) -> float:
+        _lib.decompose(rp, ci, n, h, workspace=ws, tune=tune, device=device)
+        return _lib.last_stats()["device_ms"] * 1e-3
+
+    time_fn(dict(base))  # first touch of the workspace, graph capture
+    stream.synchronize()
+    num_cu = torch.cuda.get_device_properties(dev).multi_processor_count
+    best = search_rounds(time_fn, base, num_cu, repeats)
+    c.put(key, best)
+    return best

@@ -43,3 +43,16 @@ def test_cache_round_trip(tmp_path):
     assert A.Cache(p).get("k") == {"word_bits": 128, "edges_per_wave": 4, "dense_threshold": 32}
     p.write_text("not json")
     assert A.Cache(p).get("k") is None  # a corrupt cache is ignored
+
+
+def test_round_search_keeps_the_base_and_picks_the_fastest_grid():
+    base = {"dense_threshold": 32, "word_bits": 64, "edges_per_wave": 0}
+    seen = []
+
+    def time_fn(t):
+        seen.append(t["grid_blocks"])
+        assert {k: t[k] for k in base} == base
+        return {4 * 256: 3.0, 8 * 256: 1.0, 16 * 256: 2.0}[t["grid_blocks"]]
+    best = A.search_rounds(time_fn, base, num_cu=256, repeats=2)
+    assert best == dict(base, grid_blocks=8 * 256)
+    assert sorted(set(seen)) == [p * 256 for p in A.GRID_PER_CU] and len(seen) == 6

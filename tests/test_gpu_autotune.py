@@ -44,3 +44,17 @@ def test_autotune_batch_is_exact(tmp_path):
     for g, h, t, r in zip(gs, hs, ts, rs):
         to, ro, _ = oracle.decompose(g, int(h))
         assert np.array_equal(t, to) and np.array_equal(r, ro)
+
+
+def test_round_grid_tuning_is_exact_and_cached(tmp_path):
+    # the round kernels' grid width, chosen on whole decompositions
+    from paper_2411_06405_amd import autotune as A
+    g = W.d2(n=3000)
+    cache = tmp_path / "tune.json"
+    tune = A.autotune_rounds(g.row_ptr, g.col_idx, g.n, 2, device="cuda:0", cache=cache)
+    assert set(tune) == {"word_bits", "edges_per_wave", "dense_threshold", "grid_blocks"}
+    assert any(k.endswith("|rounds") for k in A.Cache(cache).data)
+    assert A.autotune_rounds(g.row_ptr, g.col_idx, g.n, 2, device="cuda:0", cache=cache) == tune
+    t, rho = run_gpu(g, 2, tune=tune)
+    to, ro, _ = oracle.decompose(g, 2)
+    assert np.array_equal(t, to) and np.array_equal(rho, ro)
