@@ -521,6 +521,8 @@ def run_serve(args) -> dict:
                     if sess.poll(tickets[i]):
                         done_at[i] = now
                         pending.discard(i)
+                        _log(f"request {i} (n={gs[i].n}, h={hs[i]}) done at {now:.1f} s, "
+                             f"{len(pending)} pending, {N - nxt} to arrive")
             elif nxt < N:
                 time.sleep(max(0.0, min(arrivals[nxt] - now, 0.01)))
         res = [sess.result(tk) for tk in tickets]
