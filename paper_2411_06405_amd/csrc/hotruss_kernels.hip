@@ -549,7 +549,11 @@ __global__ void __launch_bounds__(256) k_mark(const Dev* __restrict__ devs) {
 // pair's witness probes spread over 1,024 threads
 constexpr uint32_t LV_THREADS = 1024;
 constexpr uint32_t LV_WAVES = LV_THREADS / WAVE;
-constexpr uint32_t LV_CAP = 1024;  // candidate pairs buffered per workgroup
+// candidate pairs buffered per workgroup: a flush comes once another
+// emission step (one candidate per thread at most) might not fit, so the
+// buffer holds two steps' worth -- bitset-word items at j >= 3 yield few
+// candidates per step, and a flush per step would dominate their time
+constexpr uint32_t LV_CAP = 2048;
 constexpr uint32_t LV_DENSE = 256; // of those, most tested on bitset rows per flush
 
 // Block-wide exclusive scan of v[0..n) (n <= LV_CAP) into out; returns the total.
