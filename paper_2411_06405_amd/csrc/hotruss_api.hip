@@ -313,7 +313,10 @@ RoundGrid plain_grid(uint64_t m, const hoTuning* tune) {
   const unsigned wide = tune && tune->grid_blocks ? tune->grid_blocks : (unsigned)num_cu() * 8;
   g.jump = std::min<unsigned>(MIN_PART, grid_for(m, 256, 4));
   g.mark = std::max(1u, std::min(wide, grid_for(m, 256)));
-  g.level = std::max(1u, std::min<unsigned>(wide, STAT_GRID) * 256 / LV_THREADS);
+  // k_level's register use leaves room for one of its 1,024-thread
+  // workgroups per CU: an eighth of the wide grid (one per CU by default)
+  // runs in a single pass, where more would queue behind the first batch
+  g.level = std::max(1u, std::min<unsigned>(wide, STAT_GRID) * 128 / LV_THREADS);
   g.support = std::min<unsigned>(wide, STAT_GRID);
   return g;
 }

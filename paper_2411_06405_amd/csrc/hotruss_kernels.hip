@@ -478,7 +478,11 @@ __device__ void mark_edge(const Dev& d, const RoundCtx& rc, bool valid, uint32_t
   }
 }
 
-__global__ void __launch_bounds__(256) k_mark(const Dev* __restrict__ devs) {
+// At most 64 registers per lane (eight waves per SIMD): the launch's 2,048
+// workgroups of 256 threads are then all resident at once on 256 CUs, so a
+// level-jump scan runs in one pass instead of leaving a second batch waiting.
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8)))
+k_mark(const Dev* __restrict__ devs) {
   const Dev& d = devs[blockIdx.y];
   Ctl* c = d.ctl;
   if (c->done || c->halt) return;
