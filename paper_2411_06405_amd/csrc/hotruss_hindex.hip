@@ -425,6 +425,7 @@ __global__ void __launch_bounds__(256) k_hx_split_mask(Hx x) {
 // Every HX_STOP_EVERY steps, at a point all lanes reach together, stop() may
 // end the scan.  Returns the algorithmic bytes this lane read, keys excluded.
 constexpr uint32_t HX_STOP_EVERY = 4;
+constexpr uint32_t HX_UNROLL = 2;   // list members per lane per step of the walk
 
 template <class F, class S>
 __device__ __forceinline__ unsigned long long hx_common(const Hx& x, uint32_t u, uint32_t v,
@@ -440,21 +441,44 @@ __device__ __forceinline__ unsigned long long hx_common(const Hx& x, uint32_t u,
     const uint32_t* Pb = x.P[0] + x.boff[b];
     const uint64_t* Lb = x.L[x.h] + (size_t)b * x.W;
     const uint32_t* Wb = x.wp + (size_t)b * x.W;
-    for (uint32_t i0 = 0; i0 < na; i0 += WAVE) {
-      const uint32_t i = i0 + lane_id();
-      if (i < na) {
-        const uint32_t w = Ma[i];
-        bytes += 12;
-        if (w != u && w != v) {
-          const uint64_t word = Lb[w >> 6];
-          if ((word >> (w & 63)) & 1ull) {
-            bytes += 4;
-            const uint32_t rb = Wb[w >> 6] + (uint32_t)__popcll(word & ((1ull << (w & 63)) - 1));
-            f(min(Pa[i], Pb[rb]));
-          }
-        }
+    // HX_UNROLL members per lane per step, each level of the dependent
+    // chain (member, probed ball word, rank word, the two keys) issued for
+    // all of them before the next: more loads in flight per wave
+    for (uint32_t i0 = 0; i0 < na; i0 += HX_UNROLL * WAVE) {
+      uint32_t w[HX_UNROLL], rb[HX_UNROLL], ka[HX_UNROLL], kb[HX_UNROLL];
+      uint64_t word[HX_UNROLL];
+      bool hit[HX_UNROLL];
+#pragma unroll
+      for (uint32_t q = 0; q < HX_UNROLL; ++q) {
+        const uint32_t i = i0 + q * WAVE + lane_id();
+        w[q] = i < na ? Ma[i] : u;
       }
-      if (++it == HX_STOP_EVERY) {
+#pragma unroll
+      for (uint32_t q = 0; q < HX_UNROLL; ++q) {
+        const bool probe = w[q] != u && w[q] != v;
+        word[q] = probe ? Lb[w[q] >> 6] : 0ull;
+      }
+#pragma unroll
+      for (uint32_t q = 0; q < HX_UNROLL; ++q) {
+        const uint32_t i = i0 + q * WAVE + lane_id();
+        if (i < na) bytes += 12;
+        hit[q] = (word[q] >> (w[q] & 63)) & 1ull;
+        rb[q] = hit[q] ? Wb[w[q] >> 6] : 0u;
+        ka[q] = hit[q] ? Pa[i] : 0u;
+      }
+#pragma unroll
+      for (uint32_t q = 0; q < HX_UNROLL; ++q) {
+        rb[q] += (uint32_t)__popcll(word[q] & ((1ull << (w[q] & 63)) - 1));
+        kb[q] = hit[q] ? Pb[rb[q]] : 0u;
+      }
+#pragma unroll
+      for (uint32_t q = 0; q < HX_UNROLL; ++q)
+        if (hit[q]) {
+          bytes += 4;
+          f(min(ka[q], kb[q]));
+        }
+      it += HX_UNROLL;
+      if (it >= HX_STOP_EVERY) {
         it = 0;
         if (stop()) break;
       }
