@@ -306,6 +306,7 @@ hoStatus run_init(const Dev& d, uint32_t* out_sup, const hoTuning* tune, hipStre
 // Launch geometry of the round kernels (x: workgroups per slot).
 struct RoundGrid {
   unsigned jump, mark, level, support;
+  unsigned lv_threads;  // k_level's workgroup shape: LV_WIDE_THREADS or LV_NARROW_THREADS
 };
 
 RoundGrid plain_grid(uint64_t m, const hoTuning* tune) {
@@ -316,7 +317,8 @@ RoundGrid plain_grid(uint64_t m, const hoTuning* tune) {
   // k_level's register use leaves room for one of its 1,024-thread
   // workgroups per CU: an eighth of the wide grid (one per CU by default)
   // runs in a single pass, where more would queue behind the first batch
-  g.level = std::max(1u, std::min<unsigned>(wide, STAT_GRID) * 128 / LV_THREADS);
+  g.level = std::max(1u, std::min<unsigned>(wide, STAT_GRID) * 128 / LV_WIDE_THREADS);
+  g.lv_threads = LV_WIDE_THREADS;
   g.support = std::min<unsigned>(wide, STAT_GRID);
   return g;
 }
@@ -328,18 +330,28 @@ RoundGrid batch_grid(uint32_t slots, const hoTuning* tune) {
   // step wait on the slot with the largest round.
   const unsigned total = tune && tune->grid_blocks ? tune->grid_blocks : (unsigned)num_cu() * 64;
   const unsigned per = std::max(4u, std::min(256u, total / std::max(1u, slots)));
-  RoundGrid g{std::min<unsigned>(MIN_PART, per), per, std::max(1u, per * 256 / LV_THREADS), per};
+  RoundGrid g{std::min<unsigned>(MIN_PART, per), per, std::max(1u, per * 256 / LV_NARROW_THREADS),
+              per, LV_NARROW_THREADS};
   return g;
 }
 
 // Kernel kinds timed in stats mode.
 enum { KT_SUPINIT = 0, KT_JUMP, KT_MARK, KT_LEVEL, KT_SUPPORT, KT_ADVANCE, KT_N };
 
+void launch_level(const Dev* devs, uint32_t S, const RoundGrid& g, hipStream_t s, uint32_t j) {
+  if (g.lv_threads == LV_WIDE_THREADS)
+    hipLaunchKernelGGL((k_level<LV_WIDE_THREADS, LV_WIDE_CAP>), dim3(g.level, S),
+                       dim3(LV_WIDE_THREADS), 0, s, devs, j);
+  else
+    hipLaunchKernelGGL((k_level<LV_NARROW_THREADS, LV_NARROW_CAP>), dim3(g.level, S),
+                       dim3(LV_NARROW_THREADS), 0, s, devs, j);
+}
+
 void launch_step(const Dev* devs, uint32_t S, uint32_t hmax, const RoundGrid& g, hipStream_t s) {
   const unsigned T = 256;
   hipLaunchKernelGGL(k_mark, dim3(g.mark, S), dim3(T), 0, s, devs);
   for (uint32_t j = 2; j <= hmax; ++j)
-    hipLaunchKernelGGL(k_level, dim3(g.level, S), dim3(LV_THREADS), 0, s, devs, j);
+    launch_level(devs, S, g, s, j);
   hipLaunchKernelGGL(k_support, dim3(g.support, S), dim3(T), 0, s, devs);
   hipLaunchKernelGGL(k_end, dim3(g.jump, S), dim3(T), 0, s, devs);
 }
@@ -428,7 +440,7 @@ hoStatus recover_step(const Dev& d, const RoundGrid& g, hipStream_t s, uint32_t 
       continue;
     }
     HOCHK(tm.begin(s));
-    if (step <= d.h) hipLaunchKernelGGL(k_level, dim3(g.level), dim3(LV_THREADS), 0, s, dp, step);
+    if (step <= d.h) launch_level(dp, 1, g, s, step);
     else hipLaunchKernelGGL(k_support, dim3(g.support), dim3(T), 0, s, dp);
     HOCHK(tm.end(s, step <= d.h ? KT_LEVEL : KT_SUPPORT));
     if (d.spart) {
@@ -456,7 +468,7 @@ hoStatus steps_host(const Dev& d, const RoundGrid& g, hipStream_t s, uint32_t fr
     bool recover = recover_first && step == from;
     if (!recover) {
       HOCHK(tm.begin(s));
-      if (step <= d.h) hipLaunchKernelGGL(k_level, dim3(g.level), dim3(LV_THREADS), 0, s, dp, step);
+      if (step <= d.h) launch_level(dp, 1, g, s, step);
       else hipLaunchKernelGGL(k_support, dim3(g.support), dim3(T), 0, s, dp);
       HOCHK(tm.end(s, step <= d.h ? KT_LEVEL : KT_SUPPORT));
       if (d.spart) {

@@ -547,21 +547,27 @@ k_mark(const Dev* __restrict__ devs) {
 }
 
 // ---- K3: ball-change events at level j >= 2 ----------------------------
-// 16 wavefronts per workgroup: the drop phase reserves list space once per
-// workgroup on device-wide counters (same-address atomics serialise at about
-// 11 ns each), so fewer, larger workgroups mean fewer of them, and a hub
-// pair's witness probes spread over 1,024 threads
-constexpr uint32_t LV_THREADS = 1024;
-constexpr uint32_t LV_WAVES = LV_THREADS / WAVE;
-// candidate pairs buffered per workgroup: a flush comes once another
-// emission step (one candidate per thread at most) might not fit, so the
-// buffer holds two steps' worth -- bitset-word items at j >= 3 yield few
-// candidates per step, and a flush per step would dominate their time
-constexpr uint32_t LV_CAP = 2048;
+// Two workgroup shapes.  A single graph runs 16 wavefronts per workgroup,
+// one workgroup per CU (its registers allow no second): the drop phase
+// reserves list space once per workgroup on device-wide counters
+// (same-address atomics serialise at about 11 ns each), so fewer, larger
+// workgroups mean fewer of them, and a hub pair's witness probes spread over
+// 1,024 threads.  Batched and served steps give every slot its own small
+// grid, most of whose workgroups find nothing to do and return at once:
+// there 256-thread workgroups pass through the CUs several at a time, where
+// 1,024-thread ones would queue one per CU.
+// The buffer holds the candidate pairs of a workgroup: a flush comes once
+// another emission step (one candidate per thread at most) might not fit, so
+// it holds at least two steps' worth -- bitset-word items at j >= 3 yield few
+// candidates per step, and a flush per step would dominate their time.
+constexpr uint32_t LV_WIDE_THREADS = 1024, LV_WIDE_CAP = 2048;    // single graph
+constexpr uint32_t LV_NARROW_THREADS = 256, LV_NARROW_CAP = 1024; // batched slots
 constexpr uint32_t LV_DENSE = 256; // of those, most tested on bitset rows per flush
 
 // Block-wide exclusive scan of v[0..n) (n <= LV_CAP) into out; returns the total.
+template <uint32_t LV_THREADS, uint32_t LV_CAP>
 __device__ uint32_t block_scan_cap(const uint32_t* v, uint32_t* out, uint32_t n, uint32_t* wsum) {
+  constexpr uint32_t LV_WAVES = LV_THREADS / WAVE;
   const uint32_t per = LV_CAP / LV_THREADS;  // entries per thread
   const uint32_t b0 = threadIdx.x * per;
   uint32_t loc[per];
@@ -594,7 +600,10 @@ __device__ uint32_t block_scan_cap(const uint32_t* v, uint32_t* out, uint32_t n,
 // the pair's probes (the live neighbours y of its lower-degree endpoint a,
 // each checked against the other endpoint's (j-1)-ball) are laid out flat
 // over all threads of the workgroup.  Pairs with no witness leave the ball.
+template <uint32_t LV_THREADS, uint32_t LV_CAP>
 __global__ void __launch_bounds__(LV_THREADS) k_level(const Dev* __restrict__ devs, uint32_t j) {
+  static_assert(LV_CAP >= 2 * LV_THREADS && LV_CAP % LV_THREADS == 0, "two emission steps fit");
+  constexpr uint32_t LV_WAVES = LV_THREADS / WAVE;
   const Dev& d = devs[blockIdx.y];
   if (j > d.h) return;  // this slot's graph has fewer levels
   __shared__ uint32_t cx[LV_CAP], cw[LV_CAP], cb[LV_CAP], cbeg[LV_CAP], cdeg[LV_CAP],
@@ -770,7 +779,7 @@ __global__ void __launch_bounds__(LV_THREADS) k_level(const Dev* __restrict__ de
       }
     }
     __syncthreads();
-    const uint32_t total = block_scan_cap(cdeg, coff, n, s_wsum);
+    const uint32_t total = block_scan_cap<LV_THREADS, LV_CAP>(cdeg, coff, n, s_wsum);
     const uint32_t ndense = min(s_ndense, LV_DENSE);
     if (counting && threadIdx.x == 0) s_stat[3] += total;
     // four probes per thread in flight: owners found in LDS first, then all

@@ -32,7 +32,11 @@ def source_sha(srcname: str) -> str:
 
 
 def short(name: str) -> str:
-    return name.split("(")[0].replace("hotruss::", "")
+    """Kernel name without namespace, parameters or template arguments."""
+    base = name.split("(")[0].replace("hotruss::", "")
+    if base.startswith("void "):
+        base = base[len("void "):]
+    return base.split("<")[0]
 
 
 def kernel_table(db: str):
