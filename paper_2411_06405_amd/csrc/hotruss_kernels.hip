@@ -513,10 +513,18 @@ k_mark(const Dev* __restrict__ devs) {
     }
   } else {
     const uint32_t nR = c->nR;
-    for (uint32_t base = wbase; base < nR; base += wstride) {
-      const uint32_t i = base + lane;
-      const bool valid = i < nR;
-      mark_edge(d, rc, valid, valid ? d.R[rc.p][i] : 0, i);
+    if (nR <= wstride / WAVE) {
+      // no more peeled edges than wavefronts: one edge per wavefront (lane 0
+      // holds it), so the 64 lanes share the writing of its work items --
+      // the rows of a hub endpoint are hundreds of items
+      const uint32_t i = wbase / WAVE;
+      if (i < nR) mark_edge(d, rc, lane == 0, lane == 0 ? d.R[rc.p][i] : 0, i);
+    } else {
+      for (uint32_t base = wbase; base < nR; base += wstride) {
+        const uint32_t i = base + lane;
+        const bool valid = i < nR;
+        mark_edge(d, rc, valid, valid ? d.R[rc.p][i] : 0, i);
+      }
     }
   }
   // clear the change marks of the previous round: the whole array of a level
