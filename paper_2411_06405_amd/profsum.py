@@ -1,6 +1,7 @@
 """Summarise rocprofv3 databases of a bench run into short text files.
 
     python -m paper_2411_06405_amd.profsum TRACE_DB FETCH_DB WRITE_DB OUTDIR TAG CMD
+    python -m paper_2411_06405_amd.profsum counters PMC_DB OUTDIR TAG CMD
 
 Writes OUTDIR/kernels_TAG.txt (per-kernel dispatch count and durations from
 --kernel-trace), OUTDIR/hbm_counters_TAG.txt (mean FETCH_SIZE / WRITE_SIZE per
@@ -8,7 +9,9 @@ dispatch, KiB) and OUTDIR/traffic_KERNEL_TAG.txt for the kernels named in
 KERNEL_SOURCES (HBM bytes per launch, scaled by what the same counters read
 for a 256 MiB device-to-device copy), and OUTDIR/traffic_whole_TAG.txt: the
 scaled bytes of every library kernel (names starting with k_) per
-decomposition, a decomposition being one dispatch of k_init_ctl.
+decomposition, a decomposition being one dispatch of k_init_ctl.  The
+counters form writes OUTDIR/counters_TAG.txt: the mean per dispatch of every
+counter of one --pmc run, per kernel.
 """
 from __future__ import annotations
 
@@ -116,5 +119,29 @@ def main(trace_db, fetch_db, write_db, outdir, tag, cmd):
             "command": cmd}, indent=1) + "\n")
 
 
+def counters_main(db, outdir, tag, cmd):
+    """Mean value per dispatch of every counter in one --pmc database, per kernel."""
+    c = sqlite3.connect(db)
+    names = [r[0] for r in c.execute("select distinct counter_name from counters_collection")]
+    names.sort()
+    rows = {}
+    for name in names:
+        for k, arr in counter_table(db, name).items():
+            rows.setdefault(short(k), {})[name] = (len(arr), float(arr.mean()))
+    lines = [f"# rocprofv3 --pmc {' '.join(names)} -- {cmd}",
+             "# kernel, dispatches, " + ", ".join(f"mean {n}" for n in names)]
+    order = sorted(rows, key=lambda k: -max(v[0] * v[1] for v in rows[k].values()))
+    for k in order:
+        cnt = max(v[0] for v in rows[k].values())
+        vals = " ".join(f"{rows[k].get(n, (0, 0.0))[1]:16.1f}" for n in names)
+        lines.append(f"{k:40s} {cnt:8d} {vals}")
+    out = Path(outdir)
+    out.mkdir(parents=True, exist_ok=True)
+    (out / f"counters_{tag}.txt").write_text("\n".join(lines) + "\n")
+
+
 if __name__ == "__main__":
-    main(*sys.argv[1:7])
+    if sys.argv[1] == "counters":
+        counters_main(*sys.argv[2:6])
+    else:
+        main(*sys.argv[1:7])
