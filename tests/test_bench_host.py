@@ -61,3 +61,24 @@ def test_traffic_only_for_the_profiled_source(tmp_path, monkeypatch):
     (tmp_path / "traffic_k_level_w.txt").write_text(json.dumps(rec))
     assert bench.recorded_traffic("k_level", "w") is None
     assert bench.recorded_traffic("k_support", "w") is None
+
+
+def test_whole_run_fields(tmp_path, monkeypatch):
+    """Counter fraction = recorded bytes / device time / 8 TB/s; traffic
+    efficiency = recorded bytes / B_alg; the recorded bytes count only while
+    taken on the current kernel source."""
+    monkeypatch.setattr(bench, "PROFILES", tmp_path)
+    rec = {"source_sha": bench.kernel_source_sha("k_level"), "bytes_per_decomposition": 4.0e12}
+    (tmp_path / "traffic_whole_w.txt").write_text(json.dumps(rec))
+    st = {"evaluations": 2.0e9, "alg_bytes": 8.0e14}
+    r = bench.whole_run(st, "w", 1000.0)
+    assert r["counter_bytes"] == 4.0e12
+    assert r["counter_frac"] == pytest.approx(4.0e12 / 1.0 / 8.0e12)
+    assert r["traffic_efficiency"] == pytest.approx(4.0e12 / 8.0e14)
+    assert r["evaluations_per_s"] == pytest.approx(2.0e9)
+    rec["source_sha"] = "0" * 16
+    (tmp_path / "traffic_whole_w.txt").write_text(json.dumps(rec))
+    r = bench.whole_run(st, "w", 1000.0)
+    assert r["counter_bytes"] is None
+    assert "counter_frac" not in r and "traffic_efficiency" not in r
+    assert r["evaluations_per_s"] == pytest.approx(2.0e9)
